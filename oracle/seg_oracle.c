@@ -1,0 +1,284 @@
+/*
+ * CPU oracle for atlas-based fiber bundle segmentation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * source with the GPU library.
+ *
+ * What it computes (Vazquez et al., "Parallel optimization of fiber bundle
+ * segmentation for massive tractography datasets"):
+ *
+ *   d_E(a_i, b_i) = || a_i - b_i ||_2                         (Eq. 1)
+ *   d_ME(a, b)    = min( max_i d_E(a_i, b_i),
+ *                        max_i d_E(a_i, b_{20-i}) )           (Eq. 2; the
+ *                   inverse order pairs point i with point 20-i, 0-based)
+ *   a fiber matches a centroid when d_ME is not above the threshold of the
+ *   centroid's bundle (section 2.3); among matching centroids the fiber takes
+ *   the bundle of the closest one (section 2.4, "Classification of fibers";
+ *   Algorithm 1 keeps the first centroid found at equal distance, i.e. the
+ *   lowest index in bundle-major order).
+ *
+ * Readings of points the paper leaves open (each is listed with its reason in
+ * the design notes of the repository):
+ *   - comparison is done on squared distances: D = d_ME^2 against
+ *     T2 = fl32(T*T); a bundle with T < 0 never matches;
+ *   - "under the threshold" is inclusive: accept iff D <= T2;
+ *   - the float32 point distance is evaluated with one fixed expression and
+ *     no other contraction:
+ *         dx = fl(a.x - b.x), dy = ..., dz = ...
+ *         d2 = fmaf(dz, dz, fmaf(dy, dy, fl(dx * dx)))
+ *     (this file must be compiled with -ffp-contract=off);
+ *   - a fiber with no matching centroid gets label -1 and distance +inf;
+ *   - the reported distance is d_ME (no length term), sqrt of D rounded once.
+ *
+ * Two evaluation modes reach the same result:
+ *   ORACLE_BRUTE  every pair, every point, both orders (the definition);
+ *   ORACLE_CUT    the paper's progressive discard (section 2.3, "Progressive
+ *                 fiber discarding", and section 2.4): center point, then the
+ *                 two end points, then four intermediate points, then all
+ *                 points, with an exit as soon as a point distance exceeds
+ *                 the threshold in an order; an order dies on its first
+ *                 exceeding point and a pair dies when both orders died.
+ *                 The four intermediate points are 4, 8, 12 and 16 (the paper
+ *                 does not name them; any choice gives the same result).
+ * Precisions:
+ *   *_f32  the float32 decision above (labels must match it bit for bit);
+ *   *_f64  the same definition in double precision with exact differences,
+ *          accept iff D64 <= (double)T * (double)T.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NP 21
+#define CENTER 10
+
+enum { ORACLE_BRUTE = 0, ORACLE_CUT = 1 };
+
+/* ---------------------------------------------------------------- float32 */
+
+static float d2_f32(const float* a, const float* b) {
+  float dx = a[0] - b[0];
+  float dy = a[1] - b[1];
+  float dz = a[2] - b[2];
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+/* Squared threshold of a bundle; -1 encodes "never matches". */
+static float thr2_f32(float t) { return t >= 0.0f ? t * t : -1.0f; }
+
+/* Definition: both orders over all 21 points. */
+void oracle_pair_f32(const float* a, const float* b, float* d_dir, float* d_inv) {
+  float md = 0.0f, mi = 0.0f;
+  for (int i = 0; i < NP; ++i) {
+    float x = d2_f32(a + 3 * i, b + 3 * i);
+    float y = d2_f32(a + 3 * i, b + 3 * (NP - 1 - i));
+    md = x > md ? x : md;
+    mi = y > mi ? y : mi;
+  }
+  *d_dir = md;
+  *d_inv = mi;
+}
+
+/* Brute evaluation of one pair: returns 1 and D when accepted. */
+static int eval_brute_f32(const float* a, const float* b, float t2, float* D) {
+  float md, mi;
+  oracle_pair_f32(a, b, &md, &mi);
+  float d = md < mi ? md : mi;
+  if (d <= t2) {
+    *D = d;
+    return 1;
+  }
+  return 0;
+}
+
+/* Progressive discard of one pair (paper's tests 1-4). */
+static int eval_cut_f32(const float* a, const float* b, float t2, float* D) {
+  static const int four[4] = {4, 8, 12, 16};
+  /* test1: the center point pairs with itself in both orders */
+  float c = d2_f32(a + 3 * CENTER, b + 3 * CENTER);
+  if (c > t2) return 0;
+  float md = c, mi = c;
+  int alive_d = 1, alive_i = 1;
+  /* test2: end points */
+  {
+    float x0 = d2_f32(a, b), x1 = d2_f32(a + 3 * (NP - 1), b + 3 * (NP - 1));
+    if (x0 > t2 || x1 > t2) alive_d = 0;
+    else { md = x0 > md ? x0 : md; md = x1 > md ? x1 : md; }
+    float y0 = d2_f32(a, b + 3 * (NP - 1)), y1 = d2_f32(a + 3 * (NP - 1), b);
+    if (y0 > t2 || y1 > t2) alive_i = 0;
+    else { mi = y0 > mi ? y0 : mi; mi = y1 > mi ? y1 : mi; }
+  }
+  if (!alive_d && !alive_i) return 0;
+  /* test3: four intermediate points, exit at the first exceeding distance */
+  for (int k = 0; k < 4 && alive_d; ++k) {
+    int i = four[k];
+    float x = d2_f32(a + 3 * i, b + 3 * i);
+    if (x > t2) alive_d = 0; else md = x > md ? x : md;
+  }
+  for (int k = 0; k < 4 && alive_i; ++k) {
+    int i = four[k];
+    float y = d2_f32(a + 3 * i, b + 3 * (NP - 1 - i));
+    if (y > t2) alive_i = 0; else mi = y > mi ? y : mi;
+  }
+  if (!alive_d && !alive_i) return 0;
+  /* test4: the remaining points */
+  for (int i = 1; i < NP - 1 && alive_d; ++i) {
+    if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16) continue;
+    float x = d2_f32(a + 3 * i, b + 3 * i);
+    if (x > t2) alive_d = 0; else md = x > md ? x : md;
+  }
+  for (int i = 1; i < NP - 1 && alive_i; ++i) {
+    if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16) continue;
+    float y = d2_f32(a + 3 * i, b + 3 * (NP - 1 - i));
+    if (y > t2) alive_i = 0; else mi = y > mi ? y : mi;
+  }
+  if (alive_d && alive_i) *D = md < mi ? md : mi;
+  else if (alive_d) *D = md;
+  else if (alive_i) *D = mi;
+  else return 0;
+  return 1;
+}
+
+static int check_args(int64_t n, int64_t m, const int32_t* bid, int32_t nb) {
+  if (n < 0 || m < 0) return -1;
+  if (m > 0 && nb <= 0) return -1;
+  for (int64_t c = 0; c < m; ++c)
+    if (bid[c] < 0 || bid[c] >= nb) return -2;
+  return 0;
+}
+
+/*
+ * labels[N] int32, dists[N] float32, best[N] int32 (winning centroid index or
+ * -1; may be NULL).  Returns 0, -1 on bad sizes, -2 on a bundle id out of
+ * range.  nthreads <= 0 uses the OpenMP default.
+ */
+int oracle_segment_f32(const float* fibers, int64_t n, const float* cen, int64_t m,
+                       const int32_t* bid, const float* thr, int32_t nb, int mode,
+                       int nthreads, int32_t* labels, float* dists, int32_t* best) {
+  int rc = check_args(n, m, bid, nb);
+  if (rc) return rc;
+  float* t2 = (float*)malloc(sizeof(float) * (size_t)(nb > 0 ? nb : 1));
+  for (int32_t b = 0; b < nb; ++b) t2[b] = thr2_f32(thr[b]);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t f = 0; f < n; ++f) {
+    const float* a = fibers + (size_t)f * 3 * NP;
+    float bestd = 0.0f;
+    int64_t bestc = -1;
+    for (int64_t c = 0; c < m; ++c) {
+      float D;
+      const float* b = cen + (size_t)c * 3 * NP;
+      float tt = t2[bid[c]];
+      int ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);
+      if (ok && (bestc < 0 || D < bestd)) {
+        bestd = D;
+        bestc = c;
+      }
+    }
+    if (bestc < 0) {
+      labels[f] = -1;
+      dists[f] = INFINITY;
+    } else {
+      labels[f] = bid[bestc];
+      dists[f] = sqrtf(bestd);
+    }
+    if (best) best[f] = (int32_t)bestc;
+  }
+  free(t2);
+  return 0;
+}
+
+/*
+ * Every accepted (fiber, centroid) pair, in fiber-major then centroid order.
+ * Writes at most cap pairs into pairs[2*k], pairs[2*k+1]; returns the total
+ * count (which may exceed cap), or a negative code.  Single-threaded.
+ */
+int64_t oracle_accepted_pairs_f32(const float* fibers, int64_t n, const float* cen, int64_t m,
+                                  const int32_t* bid, const float* thr, int32_t nb,
+                                  int64_t* pairs, int64_t cap) {
+  int rc = check_args(n, m, bid, nb);
+  if (rc) return rc;
+  int64_t cnt = 0;
+  for (int64_t f = 0; f < n; ++f) {
+    const float* a = fibers + (size_t)f * 3 * NP;
+    for (int64_t c = 0; c < m; ++c) {
+      float D;
+      if (eval_brute_f32(a, cen + (size_t)c * 3 * NP, thr2_f32(thr[bid[c]]), &D)) {
+        if (cnt < cap) {
+          pairs[2 * cnt] = f;
+          pairs[2 * cnt + 1] = c;
+        }
+        ++cnt;
+      }
+    }
+  }
+  return cnt;
+}
+
+/* ---------------------------------------------------------------- float64 */
+
+static double d2_f64(const float* a, const float* b) {
+  double dx = (double)a[0] - (double)b[0];
+  double dy = (double)a[1] - (double)b[1];
+  double dz = (double)a[2] - (double)b[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+void oracle_pair_f64(const float* a, const float* b, double* d_dir, double* d_inv) {
+  double md = 0.0, mi = 0.0;
+  for (int i = 0; i < NP; ++i) {
+    double x = d2_f64(a + 3 * i, b + 3 * i);
+    double y = d2_f64(a + 3 * i, b + 3 * (NP - 1 - i));
+    md = x > md ? x : md;
+    mi = y > mi ? y : mi;
+  }
+  *d_dir = md;
+  *d_inv = mi;
+}
+
+int oracle_segment_f64(const float* fibers, int64_t n, const float* cen, int64_t m,
+                       const int32_t* bid, const float* thr, int32_t nb, int nthreads,
+                       int32_t* labels, double* dists, int32_t* best) {
+  int rc = check_args(n, m, bid, nb);
+  if (rc) return rc;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t f = 0; f < n; ++f) {
+    const float* a = fibers + (size_t)f * 3 * NP;
+    double bestd = 0.0;
+    int64_t bestc = -1;
+    for (int64_t c = 0; c < m; ++c) {
+      double t = (double)thr[bid[c]];
+      if (!(t >= 0.0)) continue;
+      double md, mi;
+      oracle_pair_f64(a, cen + (size_t)c * 3 * NP, &md, &mi);
+      double d = md < mi ? md : mi;
+      if (d <= t * t && (bestc < 0 || d < bestd)) {
+        bestd = d;
+        bestc = c;
+      }
+    }
+    labels[f] = bestc < 0 ? -1 : bid[bestc];
+    dists[f] = bestc < 0 ? INFINITY : sqrt(bestd);
+    if (best) best[f] = (int32_t)bestc;
+  }
+  return 0;
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,18 @@
+"""Seeded synthetic inputs for fiber-bundle segmentation.
+
+This package only draws inputs (atlas centroids, bundle thresholds and subject
+fibers).  It holds none of the segmentation arithmetic, so the CPU oracle and
+the GPU library can both be fed from it without sharing any of the method.
+"""
+from .fibers import (  # noqa: F401
+    AtlasSpec,
+    SubjectSpec,
+    Atlas,
+    CONFIGS,
+    bezier_curves,
+    make_atlas,
+    make_fibers,
+    config_atlases,
+    config_subjects,
+    small_case,
+)

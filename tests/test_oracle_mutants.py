@@ -1,0 +1,60 @@
+"""Each plausible mistake planted in the oracle (on the CPU) fails a pin.
+
+The oracle source is copied, one mistake is substituted into the copy, the
+copy is compiled with the oracle's own flags, and every pin is run against
+it: at least one pin must fail.  Together with ``test_oracle_pins`` this shows
+the pins constrain every step of the oracle (point distance, inverse order,
+max/min, threshold, tie-break, label, distance, the paper's discard tests).
+"""
+import os
+
+import pytest
+
+import oracle
+import pins
+
+SRC = open(oracle.SRC).read()
+
+MUTANTS = {
+    "inverse_index_off_by_one": ("b + 3 * (NP - 1 - i)", "b + 3 * ((NP - i) % NP)"),
+    "dropped_dz_term": ("fmaf(dz, dz, fmaf(dy, dy, dx * dx))", "fmaf(dy, dy, dx * dx)"),
+    "wrong_sign": ("float dz = a[2] - b[2];", "float dz = a[2] + b[2];"),
+    "transposed_operand": ("float dy = a[1] - b[1];", "float dy = a[1] - b[2];"),
+    "no_fma_rounding": ("fmaf(dz, dz, fmaf(dy, dy, dx * dx))", "dz * dz + (dy * dy + dx * dx)"),
+    "max_of_orders": ("float d = md < mi ? md : mi;", "float d = md > mi ? md : mi;"),
+    "direct_order_only": ("float d = md < mi ? md : mi;", "float d = md;"),
+    "min_over_points": ("md = x > md ? x : md;\n    mi = y > mi ? y : mi;\n  }\n  *d_dir",
+                        "md = (i == 0 || x < md) ? x : md;\n    mi = y > mi ? y : mi;\n  }\n  *d_dir"),
+    "exclusive_threshold": ("if (d <= t2) {", "if (d < t2) {"),
+    "threshold_of_centroid": ("float tt = t2[bid[c]];", "float tt = t2[c % nb];"),
+    "last_tie_wins": ("if (ok && (bestc < 0 || D < bestd))", "if (ok && (bestc < 0 || D <= bestd))"),
+    "first_found_wins": ("if (ok && (bestc < 0 || D < bestd))", "if (ok && bestc < 0)"),
+    "label_is_centroid": ("labels[f] = bid[bestc];", "labels[f] = (int32_t)bestc;"),
+    "squared_distance_out": ("dists[f] = sqrtf(bestd);", "dists[f] = bestd;"),
+    "threshold_not_squared": ("return t >= 0.0f ? t * t : -1.0f;", "return t >= 0.0f ? t : -1.0f;"),
+    "cut_test2_inverse_wrong": ("float y0 = d2_f32(a, b + 3 * (NP - 1)), y1 = d2_f32(a + 3 * (NP - 1), b);",
+                                "float y0 = d2_f32(a, b), y1 = d2_f32(a + 3 * (NP - 1), b + 3 * (NP - 1));"),
+    "cut_test3_inverse_wrong": ("float y = d2_f32(a + 3 * i, b + 3 * (NP - 1 - i));\n    if (y > t2) alive_i = 0; else mi = y > mi ? y : mi;\n  }\n  if (!alive_d && !alive_i) return 0;\n  /* test4",
+                                "float y = d2_f32(a + 3 * i, b + 3 * i);\n    if (y > t2) alive_i = 0; else mi = y > mi ? y : mi;\n  }\n  if (!alive_d && !alive_i) return 0;\n  /* test4"),
+    "cut_skips_a_point": ("if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16) continue;\n    float x",
+                          "if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16 || i == 7) continue;\n    float x"),
+    "f64_rounded_difference": ("double dx = (double)a[0] - (double)b[0];", "double dx = (double)(a[0] - b[0]);"),
+    "f64_exclusive_threshold": ("if (d <= t * t && (bestc < 0 || d < bestd))", "if (d < t * t && (bestc < 0 || d < bestd))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    assert SRC.count(old) >= 1, f"mutation site for {name} not found"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(old, new, 1))
+    lib = oracle.compile_oracle(str(src), str(tmp_path / "libmutant.so"))
+    O = oracle.Oracle(lib)
+    caught = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(O)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"no pin catches mutant {name}"

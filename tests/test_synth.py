@@ -1,0 +1,52 @@
+"""The seeded input generator: reproducible and shaped like the workloads."""
+import numpy as np
+
+import synth
+from synth import fibers as F
+
+
+def test_reproducible_and_chunk_addressable():
+    fib1, at1 = synth.small_case(3000, 6, 5, seed=77)
+    fib2, at2 = synth.small_case(3000, 6, 5, seed=77)
+    assert np.array_equal(fib1, fib2) and np.array_equal(at1.centroids, at2.centroids)
+    subj = synth.SubjectSpec(F.CHUNK + 500, 2.0, (0.3,))
+    whole = synth.make_fibers([at1], subj, 5)
+    part = synth.make_fibers([at1], subj, 5, start=F.CHUNK - 100, count=300)
+    assert np.array_equal(part, whole[F.CHUNK - 100:F.CHUNK + 200])
+
+
+def test_centroid_shapes():
+    spec = synth.AtlasSpec(10, 30, 20.0, 80.0, 5.0, 8.0)
+    at = synth.make_atlas(spec, 3)
+    c = at.centroids.astype(np.float64)
+    assert at.centroids.dtype == np.float32 and c.shape == (300, 21, 3)
+    assert (c >= -1e-4).all() and (c <= F.BOX + 1e-4).all()
+    chord = np.linalg.norm(np.diff(c, axis=1), axis=2)
+    assert (chord.max(1) <= 1.25 * chord.min(1) * (1 + 1e-5)).all()
+    length = chord.sum(1)
+    assert length.min() > 20.0 * 0.95 and length.max() < 80.0 * 1.0001
+    assert np.array_equal(at.bundle_id, np.arange(300) // 30)
+    assert ((at.thresholds >= 5.0) & (at.thresholds <= 8.0)).all()
+
+
+def test_config_shapes():
+    for cfg, (m, b) in {1: (800, 40), 2: (3600, 36), 3: (10000, 100), 4: (20000, 200)}.items():
+        spec = synth.CONFIGS[cfg]["atlases"][0]
+        assert spec.n_centroids == m and spec.n_bundles == b
+    assert synth.config_subjects(3)[0].n_fibers == 4_145_000
+    s5 = synth.config_subjects(5)
+    assert len(s5) == 16 and all(300_000 <= s.n_fibers <= 4_100_000 for s in s5)
+    assert [a.n_centroids for a in synth.CONFIGS[5]["atlases"]] == [3600, 10000]
+
+
+def test_matched_fraction():
+    spec = synth.AtlasSpec(4, 5, 20.0, 80.0, 5.0, 8.0)
+    at = synth.make_atlas(spec, 9)
+    subj = synth.SubjectSpec(2000, 0.0, (0.5,))
+    fib = synth.make_fibers([at], subj, 9)
+    # with sigma = 0 a matched fiber is an exact copy of a centroid, maybe reversed
+    cen = at.centroids.reshape(20, -1)
+    fwd = (fib.reshape(2000, 1, -1) == cen[None]).all(2).any(1)
+    rev = (fib[:, ::-1].reshape(2000, 1, -1) == cen[None]).all(2).any(1)
+    assert (fwd | rev).sum() == 1000
+    assert 400 < rev.sum() < 600
