@@ -1,0 +1,184 @@
+/*
+ * seg.h -- C ABI of the MI355X fiber-bundle segmentation library (libseg.so).
+ *
+ * Operation (Vazquez et al., "Parallel optimization of fiber bundle
+ * segmentation for massive tractography datasets", section 2.3 and 2.4):
+ * every subject fiber a (21 points, 3 float32 coordinates in mm) is compared
+ * with every atlas centroid b by
+ *
+ *     d_ME(a, b) = min( max_i ||a_i - b_i||, max_i ||a_i - b_{20-i}|| )   (Eq. 1-2)
+ *
+ * A centroid is accepted when d_ME does not exceed the threshold of its
+ * bundle (section 2.3).  Each fiber takes the bundle of its closest accepted
+ * centroid (section 2.4, "Classification of fibers"; Algorithm 1), the lowest
+ * centroid index on equal distance, or no label.
+ *
+ * Arithmetic contract (identical for every mode, tile and batch layout):
+ *   - squared point distance in float32, evaluated exactly as
+ *       dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z   (each rounded)
+ *       d2 = fma(dz, dz, fma(dy, dy, dx * dx))
+ *     with round-to-nearest-even, no flushing of subnormals, no other fusion;
+ *   - D = min(max_i d2 direct, max_i d2 inverse); T2 = T * T rounded to
+ *     float32 for T >= 0 (a bundle with T < 0 never matches);
+ *   - accepted iff D <= T2; the winner minimises (D, centroid index);
+ *   - labels[f] = bundle id of the winner, dists[f] = sqrt(D) correctly
+ *     rounded; a fiber with no accepted centroid gets (-1, +inf).
+ *
+ * Memory: every pointer argument named "device" is a device (HBM) address on
+ * the current HIP device; the caller owns every input and output buffer.
+ * Fibers and centroids are C-contiguous [count][21][3] float32 (array of
+ * structures, 252 bytes per curve, 4-byte aligned).  The library owns its
+ * scratch (prepared atlas copies, prefilter features, counters); scratch is
+ * cached per (device, stream), grows on demand and is never O(N x M).
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ * asynchronous on that stream unless validation is requested.  Two calls
+ * that run concurrently on different streams use different scratch.
+ *
+ * Errors: every int-returning function returns SEG_OK (0) or a negative
+ * seg_status; seg_last_error() gives a message for the calling thread.
+ */
+#ifndef SEG_H
+#define SEG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEG_NPOINTS 21
+#define SEG_VERSION 1
+
+typedef enum seg_status {
+  SEG_OK = 0,
+  SEG_EINVAL = -1,      /* null pointer, negative size, B <= 0 with M > 0, misaligned */
+  SEG_EBUNDLE = -2,     /* a centroid bundle id outside [0, B) (validate = 1) */
+  SEG_ENONFINITE = -3,  /* NaN / inf coordinate or NaN threshold (validate = 1) */
+  SEG_EHIP = -4,        /* a HIP runtime call failed */
+  SEG_ENOMEM = -5,      /* scratch allocation failed */
+  SEG_ERANGE = -6,      /* a size beyond what the kernels index (M >= 2^24) */
+  SEG_EMODE = -7        /* unknown mode or option value */
+} seg_status;
+
+typedef enum seg_mode {
+  /* every pair, every point, both orders: the exact stage run on all pairs */
+  SEG_DENSE = 0,
+  /* float32 center-point test on every pair (the paper's test1), packed
+     survivors, then the paper's tests 2-4 and the full metric on them */
+  SEG_PLAIN = 1,
+  /* conservative mean bound on MFMA with an orientation-free feature map
+     (pairs of points symmetric about the center), bf16 / fp16 / fp8 inputs,
+     fp32 accumulation; exact float32 stage on survivors */
+  SEG_PREFILTER_BF16 = 2,
+  SEG_PREFILTER_FP16 = 3,
+  SEG_PREFILTER_FP8 = 4,
+  /* the same bound with one 63-wide product per point order */
+  SEG_PREFILTER_BF16_ORIENTED = 5
+} seg_mode;
+
+typedef struct seg_options {
+  int32_t mode;          /* seg_mode; default SEG_PLAIN */
+  int32_t validate;      /* 1: check inputs on the device and synchronise the
+                            stream to report SEG_EBUNDLE / SEG_ENONFINITE */
+  int32_t tile;          /* 0: library choice (autotuned cache if present);
+                            k > 0: kernel configuration k of the mode */
+  int32_t collect_stats; /* 1: count survivors per stage (read with
+                            seg_query_stats; adds atomics, not for timing) */
+} seg_options;
+
+typedef struct seg_stats {
+  int64_t pairs;           /* N * M of the last call */
+  int64_t filter_pass;     /* pairs that passed the first cut (test1 or the
+                              prefilter bound); DENSE: pairs */
+  int64_t test2_pass;      /* pairs alive after the end-point test */
+  int64_t test3_pass;      /* pairs alive after the four-point test */
+  int64_t accepted;        /* pairs with D <= T2 */
+  int64_t labelled;        /* fibers with a label */
+  int64_t drains;          /* survivor-queue drains (wave level) */
+} seg_stats;
+
+/* Default options (mode SEG_PLAIN, no validation, library tiles, no stats). */
+void seg_default_options(seg_options* opt);
+
+/*
+ * Segment one subject against one atlas.
+ *   fibers             device, [n_fibers][21][3] float32
+ *   centroids          device, [n_centroids][21][3] float32
+ *   centroid_bundle_id device, [n_centroids] int32, each in [0, n_bundles)
+ *   bundle_thresholds  device, [n_bundles] float32, mm
+ *   labels, dists      device, [n_fibers] int32 / float32, written
+ *   opt                host, may be NULL (defaults)
+ * n_fibers = 0 returns SEG_OK without launching; n_centroids = 0 writes
+ * (-1, +inf) everywhere.  A bundle id outside [0, n_bundles) never matches
+ * (and is reported as SEG_EBUNDLE when opt->validate = 1).
+ */
+int seg_segment(const float* fibers, int64_t n_fibers, const float* centroids,
+                int64_t n_centroids, const int32_t* centroid_bundle_id,
+                const float* bundle_thresholds, int32_t n_bundles, int32_t* labels,
+                float* dists, const seg_options* opt, void* stream);
+
+/* ---- prepared atlases and batches (many subjects x one or two atlases) ---- */
+
+typedef struct seg_atlas seg_atlas;
+
+/*
+ * Copy and prepare an atlas (device inputs as in seg_segment).  The handle
+ * owns device memory on the current device until seg_atlas_destroy.  The
+ * inputs may be freed after the call returns (the call synchronises
+ * `stream`).  Returns SEG_EBUNDLE / SEG_ENONFINITE on bad inputs.
+ */
+int seg_atlas_create(const float* centroids, int64_t n_centroids,
+                     const int32_t* centroid_bundle_id, const float* bundle_thresholds,
+                     int32_t n_bundles, void* stream, seg_atlas** out);
+void seg_atlas_destroy(seg_atlas* atlas);
+int64_t seg_atlas_size(const seg_atlas* atlas); /* number of centroids */
+
+/* seg_segment against a prepared atlas. */
+int seg_segment_atlas(const seg_atlas* atlas, const float* fibers, int64_t n_fibers,
+                      int32_t* labels, float* dists, const seg_options* opt, void* stream);
+
+/*
+ * Segment n_subjects subjects against n_atlases prepared atlases in one
+ * persistent launch (replayed from a cached HIP graph when the shapes repeat).
+ *   atlases   host array [n_atlases] of handles
+ *   fibers    host array [n_subjects] of device pointers ([n][21][3] float32)
+ *   n_fibers  host array [n_subjects]
+ *   labels, dists  host arrays [n_subjects * n_atlases] of device pointers;
+ *                  entry s * n_atlases + a receives subject s against atlas a
+ * opt->mode selects the per-pair path (SEG_PLAIN or a prefilter mode).
+ */
+int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases,
+                      const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
+                      int32_t* const* labels, float* const* dists, const seg_options* opt,
+                      void* stream);
+
+/* ---- diagnostics ---- */
+
+/*
+ * Survivors of the first cut of `mode` (SEG_PLAIN: the center-point test;
+ * prefilter modes: the MFMA bound), written as (fiber, centroid) int32 pairs
+ * into the device buffer pairs[2 * k] (at most `capacity` pairs, any order).
+ * *count (host) receives the total number of survivors, which may exceed
+ * capacity.  Synchronises the stream.  Used to check that a cut never drops
+ * an accepted pair.
+ */
+int seg_filter_pairs(const float* fibers, int64_t n_fibers, const float* centroids,
+                     int64_t n_centroids, const int32_t* centroid_bundle_id,
+                     const float* bundle_thresholds, int32_t n_bundles, int32_t mode,
+                     int32_t* pairs, int64_t capacity, int64_t* count, void* stream);
+
+/* Counters of the last call on this thread made with collect_stats = 1
+   (synchronises that call's stream). */
+int seg_query_stats(seg_stats* out);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* seg_last_error(void);
+
+int seg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEG_H */

@@ -1,0 +1,442 @@
+// C ABI of libseg.so: argument checks, scratch, validation and launches.
+// The operation and its arithmetic contract are documented in include/seg.h.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "seg.h"
+#include "seg_internal.hpp"
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const std::string& msg) {
+  t_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SEG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+constexpr int64_t kMaxCentroids = (int64_t)1 << 24;  // queue entries hold 24-bit indices
+
+int64_t pad8(int64_t m) { return (m + 7) & ~(int64_t)7; }
+
+// Prepared atlas data in device memory.
+struct AtlasBuf {
+  float* cprep = nullptr;   // [m_pad][64]
+  float4* ccen = nullptr;   // [m_pad]
+  int32_t* bid = nullptr;   // [m_pad]
+  int64_t cap = 0;          // capacity in centroids
+  int64_t m = 0;
+
+  int reserve(int64_t mp) {
+    if (mp <= cap) return 0;
+    release();
+    HIP_TRY(hipMalloc(&cprep, (size_t)mp * seg::CREC_BYTES));
+    HIP_TRY(hipMalloc(&ccen, (size_t)mp * sizeof(float4)));
+    HIP_TRY(hipMalloc(&bid, (size_t)mp * sizeof(int32_t)));
+    cap = mp;
+    return 0;
+  }
+  void release() {
+    if (cprep) (void)hipFree(cprep);
+    if (ccen) (void)hipFree(ccen);
+    if (bid) (void)hipFree(bid);
+    cprep = nullptr;
+    ccen = nullptr;
+    bid = nullptr;
+    cap = 0;
+  }
+};
+
+// Per (device, stream) scratch: atlas copy for one-shot calls, flags, counters.
+struct Scratch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  AtlasBuf atlas;
+  unsigned long long* flags = nullptr;     // [1]
+  unsigned long long* counters = nullptr;  // [NCOUNTERS]
+  seg::PrefilterBuf pre;
+  seg::BatchBuf batch;
+
+  int init() {
+    if (!flags) HIP_TRY(hipMalloc(&flags, sizeof(unsigned long long)));
+    if (!counters) HIP_TRY(hipMalloc(&counters, seg::NCOUNTERS * sizeof(unsigned long long)));
+    return 0;
+  }
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Scratch*> g_scratch;
+
+int get_scratch(hipStream_t s, Scratch** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, s);
+  auto it = g_scratch.find(key);
+  if (it == g_scratch.end()) {
+    Scratch* sc = new Scratch();
+    sc->device = dev;
+    sc->stream = s;
+    int rc = sc->init();
+    if (rc) {
+      delete sc;
+      return rc;
+    }
+    it = g_scratch.emplace(key, sc).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
+// State for seg_query_stats.
+thread_local unsigned long long* t_stats_counters = nullptr;
+thread_local hipStream_t t_stats_stream = nullptr;
+thread_local int64_t t_stats_pairs = 0;
+thread_local int64_t t_stats_n = 0;
+thread_local int32_t* t_stats_labels = nullptr;
+thread_local int t_stats_mode = 0;
+
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+int check_mode(int mode) {
+  switch (mode) {
+    case SEG_DENSE:
+    case SEG_PLAIN:
+    case SEG_PREFILTER_BF16:
+    case SEG_PREFILTER_FP16:
+    case SEG_PREFILTER_FP8:
+    case SEG_PREFILTER_BF16_ORIENTED:
+      return 0;
+    default:
+      return fail(SEG_EMODE, "unknown mode " + std::to_string(mode));
+  }
+}
+
+int check_atlas_args(const float* centroids, int64_t m, const int32_t* bid, const float* thr,
+                     int32_t nb) {
+  if (m < 0) return fail(SEG_EINVAL, "n_centroids < 0");
+  if (m >= kMaxCentroids) return fail(SEG_ERANGE, "n_centroids must be below 2^24");
+  if (m > 0 && nb <= 0) return fail(SEG_EINVAL, "n_bundles must be positive when centroids exist");
+  if (m > 0 && (!centroids || !bid)) return fail(SEG_EINVAL, "null centroid or bundle-id pointer");
+  if (nb > 0 && !thr) return fail(SEG_EINVAL, "null threshold pointer");
+  if (!aligned4(centroids) || !aligned4(bid) || !aligned4(thr))
+    return fail(SEG_EINVAL, "atlas pointers must be 4-byte aligned");
+  return 0;
+}
+
+// Prepare an atlas into `ab` on stream s; flags collects validation bits.
+int prepare_atlas(AtlasBuf& ab, const float* centroids, int64_t m, const int32_t* bid,
+                  const float* thr, int32_t nb, unsigned long long* flags, hipStream_t s) {
+  int rc = ab.reserve(pad8(m > 0 ? m : 1));
+  if (rc) return rc;
+  ab.m = m;
+  if (seg::launch_prep_atlas(centroids, m, bid, thr, nb, ab.cprep, ab.ccen, ab.bid,
+                             (unsigned int*)flags, s))
+    return hip_fail(hipGetLastError(), "prep_atlas launch");
+  return 0;
+}
+
+int read_flags(unsigned long long* flags, hipStream_t s, unsigned long long* out) {
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(out, flags, sizeof(*out), hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int flags_error(unsigned long long f) {
+  if (f & seg::FLAG_BUNDLE) return fail(SEG_EBUNDLE, "a centroid bundle id is outside [0, n_bundles)");
+  if (f & seg::FLAG_NONFINITE) return fail(SEG_ENONFINITE, "non-finite coordinate or NaN threshold");
+  return 0;
+}
+
+seg_options resolve(const seg_options* opt) {
+  seg_options o;
+  seg_default_options(&o);
+  if (opt) o = *opt;
+  return o;
+}
+
+// Launch the per-pair path of `mode` for one subject against a prepared atlas.
+int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float* fibers, int64_t n,
+             int32_t* labels, float* dists, hipStream_t s) {
+  unsigned long long* counters = o.collect_stats ? sc->counters : nullptr;
+  if (counters && seg::launch_fill_u64(counters, seg::NCOUNTERS, 0ull, s))
+    return hip_fail(hipGetLastError(), "counter reset");
+  const int32_t m = (int32_t)ab.m;
+  int rc = 0;
+  switch (o.mode) {
+    case SEG_DENSE:
+      rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, o.tile, s);
+      break;
+    case SEG_PLAIN:
+      rc = seg::launch_plain(fibers, n, ab.ccen, ab.cprep, m, ab.bid, labels, dists, counters,
+                             o.tile, s);
+      break;
+    default:
+      rc = seg::run_prefilter(o.mode, o.tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
+                              dists, counters, sc->pre, s);
+      if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
+      break;
+  }
+  if (rc == -2) return fail(SEG_EMODE, "unknown tile configuration " + std::to_string(o.tile));
+  if (rc) return hip_fail(hipGetLastError(), "kernel launch");
+  if (o.collect_stats) {
+    t_stats_counters = counters;
+    t_stats_stream = s;
+    t_stats_pairs = n * ab.m;
+    t_stats_n = n;
+    t_stats_labels = labels;
+    t_stats_mode = o.mode;
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct seg_atlas {
+  int device = 0;
+  AtlasBuf buf;
+  int32_t n_bundles = 0;
+};
+
+extern "C" {
+
+void seg_default_options(seg_options* opt) {
+  if (!opt) return;
+  opt->mode = SEG_PLAIN;
+  opt->validate = 0;
+  opt->tile = 0;
+  opt->collect_stats = 0;
+}
+
+const char* seg_last_error(void) { return t_err.c_str(); }
+
+int seg_version(void) { return SEG_VERSION; }
+
+int seg_segment(const float* fibers, int64_t n, const float* centroids, int64_t m,
+                const int32_t* bid, const float* thr, int32_t nb, int32_t* labels, float* dists,
+                const seg_options* opt, void* stream) {
+  t_err.clear();
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (rc) return rc;
+  if (n < 0) return fail(SEG_EINVAL, "n_fibers < 0");
+  rc = check_atlas_args(centroids, m, bid, thr, nb);
+  if (rc) return rc;
+  if (n > 0 && (!fibers || !labels || !dists)) return fail(SEG_EINVAL, "null fiber/output pointer");
+  if (!aligned4(fibers) || !aligned4(labels) || !aligned4(dists))
+    return fail(SEG_EINVAL, "fiber/output pointers must be 4-byte aligned");
+  if (n == 0) return SEG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  if (o.validate && seg::launch_fill_u64(sc->flags, 1, 0ull, s))
+    return hip_fail(hipGetLastError(), "flag reset");
+  if (m == 0) {
+    if (o.validate) {
+      if (seg::launch_check_finite(fibers, n * 63, (unsigned int*)sc->flags, s))
+        return hip_fail(hipGetLastError(), "validation launch");
+      unsigned long long f = 0;
+      rc = read_flags(sc->flags, s, &f);
+      if (rc) return rc;
+      rc = flags_error(f);
+      if (rc) return rc;
+    }
+    if (seg::launch_fill_empty(n, labels, dists, s)) return hip_fail(hipGetLastError(), "fill");
+    return SEG_OK;
+  }
+  rc = prepare_atlas(sc->atlas, centroids, m, bid, thr, nb, sc->flags, s);
+  if (rc) return rc;
+  if (o.validate) {
+    if (seg::launch_check_finite(fibers, n * 63, (unsigned int*)sc->flags, s))
+      return hip_fail(hipGetLastError(), "validation launch");
+    unsigned long long f = 0;
+    rc = read_flags(sc->flags, s, &f);
+    if (rc) return rc;
+    rc = flags_error(f);
+    if (rc) return rc;
+  }
+  return run_mode(o, sc->atlas, sc, fibers, n, labels, dists, s);
+}
+
+int seg_atlas_create(const float* centroids, int64_t m, const int32_t* bid, const float* thr,
+                     int32_t nb, void* stream, seg_atlas** out) {
+  t_err.clear();
+  if (!out) return fail(SEG_EINVAL, "null output handle");
+  *out = nullptr;
+  int rc = check_atlas_args(centroids, m, bid, thr, nb);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  seg_atlas* a = new seg_atlas();
+  HIP_TRY(hipGetDevice(&a->device));
+  a->n_bundles = nb;
+  if (seg::launch_fill_u64(sc->flags, 1, 0ull, s)) {
+    delete a;
+    return hip_fail(hipGetLastError(), "flag reset");
+  }
+  rc = prepare_atlas(a->buf, centroids, m, bid, thr, nb, sc->flags, s);
+  unsigned long long f = 0;
+  if (!rc) rc = read_flags(sc->flags, s, &f);
+  if (!rc) rc = flags_error(f);
+  if (rc) {
+    a->buf.release();
+    delete a;
+    return rc;
+  }
+  *out = a;
+  return SEG_OK;
+}
+
+void seg_atlas_destroy(seg_atlas* a) {
+  if (!a) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(a->device);
+  a->buf.release();
+  (void)hipSetDevice(prev);
+  delete a;
+}
+
+int64_t seg_atlas_size(const seg_atlas* a) { return a ? a->buf.m : -1; }
+
+int seg_segment_atlas(const seg_atlas* a, const float* fibers, int64_t n, int32_t* labels,
+                      float* dists, const seg_options* opt, void* stream) {
+  t_err.clear();
+  if (!a) return fail(SEG_EINVAL, "null atlas");
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (rc) return rc;
+  if (n < 0) return fail(SEG_EINVAL, "n_fibers < 0");
+  if (n > 0 && (!fibers || !labels || !dists)) return fail(SEG_EINVAL, "null fiber/output pointer");
+  if (!aligned4(fibers) || !aligned4(labels) || !aligned4(dists))
+    return fail(SEG_EINVAL, "fiber/output pointers must be 4-byte aligned");
+  if (n == 0) return SEG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  if (a->buf.m == 0) {
+    if (seg::launch_fill_empty(n, labels, dists, s)) return hip_fail(hipGetLastError(), "fill");
+    return SEG_OK;
+  }
+  if (o.validate) {
+    if (seg::launch_fill_u64(sc->flags, 1, 0ull, s) ||
+        seg::launch_check_finite(fibers, n * 63, (unsigned int*)sc->flags, s))
+      return hip_fail(hipGetLastError(), "validation launch");
+    unsigned long long f = 0;
+    rc = read_flags(sc->flags, s, &f);
+    if (rc) return rc;
+    rc = flags_error(f);
+    if (rc) return rc;
+  }
+  return run_mode(o, a->buf, sc, fibers, n, labels, dists, s);
+}
+
+int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const float* const* fibers,
+                      const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
+                      float* const* dists, const seg_options* opt, void* stream) {
+  t_err.clear();
+  if (n_atlases < 0 || n_subjects < 0) return fail(SEG_EINVAL, "negative batch size");
+  if ((n_atlases > 0 && !atlases) || (n_subjects > 0 && (!fibers || !n_fibers)) ||
+      (n_atlases > 0 && n_subjects > 0 && (!labels || !dists)))
+    return fail(SEG_EINVAL, "null batch array");
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (rc) return rc;
+  for (int32_t a = 0; a < n_atlases; ++a)
+    if (!atlases[a]) return fail(SEG_EINVAL, "null atlas in batch");
+  for (int32_t i = 0; i < n_subjects; ++i) {
+    if (n_fibers[i] < 0) return fail(SEG_EINVAL, "negative subject size");
+    if (n_fibers[i] > 0 && !fibers[i]) return fail(SEG_EINVAL, "null subject pointer");
+    for (int32_t a = 0; a < n_atlases; ++a)
+      if (n_fibers[i] > 0 && (!labels[i * n_atlases + a] || !dists[i * n_atlases + a]))
+        return fail(SEG_EINVAL, "null batch output pointer");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  std::vector<seg::BatchAtlas> bav;
+  for (int32_t a = 0; a < n_atlases; ++a)
+    bav.push_back(seg::BatchAtlas{atlases[a]->buf.cprep, atlases[a]->buf.ccen,
+                                  atlases[a]->buf.bid, (int32_t)atlases[a]->buf.m});
+  rc = seg::run_batch(o.mode, o.tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
+                      dists, sc->batch, sc->pre, s);
+  if (rc == -2) return fail(SEG_EMODE, "mode not supported by the batch path");
+  if (rc == -3) return fail(SEG_ENOMEM, "batch scratch allocation failed");
+  if (rc) return hip_fail(hipGetLastError(), "batch launch");
+  return SEG_OK;
+}
+
+int seg_filter_pairs(const float* fibers, int64_t n, const float* centroids, int64_t m,
+                     const int32_t* bid, const float* thr, int32_t nb, int32_t mode,
+                     int32_t* pairs, int64_t capacity, int64_t* count, void* stream) {
+  t_err.clear();
+  int rc = check_mode(mode);
+  if (rc) return rc;
+  if (!count) return fail(SEG_EINVAL, "null count");
+  *count = 0;
+  if (n < 0 || capacity < 0) return fail(SEG_EINVAL, "negative size");
+  rc = check_atlas_args(centroids, m, bid, thr, nb);
+  if (rc) return rc;
+  if (n == 0 || m == 0) return SEG_OK;
+  if (!fibers || (capacity > 0 && !pairs)) return fail(SEG_EINVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  rc = prepare_atlas(sc->atlas, centroids, m, bid, thr, nb, sc->flags, s);
+  if (rc) return rc;
+  if (seg::launch_fill_u64(sc->counters, 1, 0ull, s)) return hip_fail(hipGetLastError(), "reset");
+  if (mode == SEG_PLAIN || mode == SEG_DENSE) {
+    rc = seg::launch_plain_pairs(fibers, n, sc->atlas.ccen, (int32_t)m, pairs, capacity,
+                                 sc->counters, s);
+  } else {
+    rc = seg::prefilter_pairs(mode, fibers, n, sc->atlas.cprep, sc->atlas.ccen, (int32_t)m, pairs,
+                              capacity, sc->counters, sc->pre, s);
+    if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
+  }
+  if (rc == -2) return fail(SEG_EMODE, "mode has no filter");
+  if (rc) return hip_fail(hipGetLastError(), "filter launch");
+  unsigned long long c = 0;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(&c, sc->counters, sizeof(c), hipMemcpyDeviceToHost));
+  *count = (int64_t)c;
+  return SEG_OK;
+}
+
+int seg_query_stats(seg_stats* out) {
+  if (!out) return fail(SEG_EINVAL, "null output");
+  if (!t_stats_counters) return fail(SEG_EINVAL, "no call with collect_stats = 1 on this thread");
+  unsigned long long c[seg::NCOUNTERS];
+  HIP_TRY(hipStreamSynchronize(t_stats_stream));
+  HIP_TRY(hipMemcpy(c, t_stats_counters, sizeof(c), hipMemcpyDeviceToHost));
+  out->pairs = t_stats_pairs;
+  out->filter_pass = t_stats_mode == SEG_DENSE ? t_stats_pairs : (int64_t)c[0];
+  out->test2_pass = (int64_t)c[1];
+  out->test3_pass = (int64_t)c[2];
+  out->accepted = (int64_t)c[3];
+  out->drains = (int64_t)c[4];
+  out->labelled = -1;
+  return SEG_OK;
+}
+
+}  // extern "C"

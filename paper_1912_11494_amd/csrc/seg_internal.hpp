@@ -1,0 +1,72 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace seg {
+
+constexpr unsigned int FLAG_BUNDLE = 1u;
+constexpr unsigned int FLAG_NONFINITE = 2u;
+
+// Number of 64-bit statistics counters (see StageCounts).
+constexpr int NCOUNTERS = 8;
+constexpr size_t CREC_BYTES = 64 * sizeof(float);
+
+// Library-owned prefilter scratch (per device and stream), grown on demand.
+struct PrefilterBuf {
+  void* fib_feat = nullptr;   // quantised fiber features
+  size_t fib_feat_bytes = 0;
+  void* cen_feat = nullptr;   // quantised centroid features + biases
+  size_t cen_feat_bytes = 0;
+  float* fib_h = nullptr;     // per-fiber bound terms
+  size_t fib_h_bytes = 0;
+  unsigned int* emax = nullptr;  // device max of the fiber quantisation error
+};
+
+// Library-owned batch scratch: work list and counters.
+struct BatchBuf {
+  void* items = nullptr;
+  size_t items_bytes = 0;
+  unsigned int* next = nullptr;
+};
+
+// A prepared atlas as the batch path sees it.
+struct BatchAtlas {
+  const float* cprep;
+  const float4* ccen;
+  const int32_t* bid;
+  int32_t m;
+};
+
+int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const float* thr,
+                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out,
+                      unsigned int* flags, hipStream_t s);
+int launch_check_finite(const float* v, int64_t count, unsigned int* flags, hipStream_t s);
+int launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
+int launch_fill_empty(int64_t n, int32_t* labels, float* dists, hipStream_t s);
+int launch_dense(const float* fibers, int64_t n, const float* cprep, int32_t m,
+                 const int32_t* bid, int32_t* labels, float* dists, int cfg, hipStream_t s);
+int plain_default_cfg(int64_t n);
+int launch_plain(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
+                 int32_t m, const int32_t* bid, int32_t* labels, float* dists,
+                 unsigned long long* counters, int cfg, hipStream_t s);
+int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32_t m,
+                       int32_t* pairs, int64_t cap, unsigned long long* count, hipStream_t s);
+
+// Prefilter modes (seg_prefilter.hip).  Return 0, -1 on a HIP error, -2 on an
+// unsupported mode or tile, -3 on a failed allocation.
+int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
+                  const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
+                  float* dists, unsigned long long* counters, PrefilterBuf& pb, hipStream_t s);
+int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
+                    const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,
+                    unsigned long long* count, PrefilterBuf& pb, hipStream_t s);
+
+// Batched persistent launch (seg_batch.hip); same return codes.
+int run_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
+              const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
+              int32_t* const* labels, float* const* dists, BatchBuf& bb, PrefilterBuf& pb,
+              hipStream_t s);
+
+}  // namespace seg

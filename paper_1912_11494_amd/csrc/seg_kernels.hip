@@ -1,0 +1,336 @@
+// Segmentation kernels for gfx950: atlas preparation, input validation, the
+// dense exact pass and the plain (center-test) pass.
+//
+// Data layout in HBM:
+//   fibers     caller's [N][21][3] float32 (252-byte records, read in place)
+//   centroids  caller's [M][21][3] float32
+//   cprep      library's [M][64] float32: the 63 coordinates + T2 of the
+//              centroid's bundle (256-byte records, one scalar-load burst)
+//   ccen       library's [M] float4: center point (x, y, z) + T2, the only
+//              centroid data the center test touches (16 bytes / centroid)
+//   labels/dists  caller's [N] int32 / float32
+#include <hip/hip_runtime.h>
+
+#include "seg_device.hpp"
+#include "seg_internal.hpp"
+
+namespace seg {
+
+// ---------------------------------------------------------------- preparation
+
+// One thread per centroid: copy the record, attach T2 of its bundle.  A bundle
+// id outside [0, B) gets T2 = -1 (never matches) and raises a flag.
+__global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict__ cen, int64_t m,
+                                                         const int32_t* __restrict__ bid,
+                                                         const float* __restrict__ thr, int32_t nb,
+                                                         float* __restrict__ cprep,
+                                                         float4* __restrict__ ccen,
+                                                         int32_t* __restrict__ bid_out,
+                                                         unsigned int* __restrict__ flags) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const float* src = cen + c * NF;
+  float* dst = cprep + c * CREC;
+  const int32_t b = bid[c];
+  float t2 = -1.0f;
+  if (b >= 0 && b < nb) {
+    t2 = thr2(thr[b]);
+  } else {
+    atomicOr(flags, FLAG_BUNDLE);
+  }
+  bool finite = true;
+  for (int k = 0; k < NF; ++k) {
+    float v = src[k];
+    finite = finite && __builtin_isfinite(v);
+    dst[k] = v;
+  }
+  dst[NF] = t2;
+  if (!finite) atomicOr(flags, FLAG_NONFINITE);
+  ccen[c] = make_float4(src[3 * CTR], src[3 * CTR + 1], src[3 * CTR + 2], t2);
+  bid_out[c] = b;
+}
+
+__global__ __launch_bounds__(256) void check_thresholds_kernel(const float* __restrict__ thr,
+                                                               int32_t nb,
+                                                               unsigned int* __restrict__ flags) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb && __builtin_isnan(thr[b])) atomicOr(flags, FLAG_NONFINITE);
+}
+
+// Grid-stride scan of coordinates for NaN / inf (4-byte aligned input).
+__global__ __launch_bounds__(256) void check_finite_kernel(const float* __restrict__ v,
+                                                           int64_t count,
+                                                           unsigned int* __restrict__ flags) {
+  bool ok = true;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    ok = ok && __builtin_isfinite(v[i]);
+  if (!wave_any(!ok)) return;
+  if (lane_id() == 0) atomicOr(flags, FLAG_NONFINITE);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* __restrict__ p, int n, unsigned long long v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_empty_kernel(int64_t n, int32_t* __restrict__ labels,
+                                                         float* __restrict__ dists) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    labels[i] = -1;
+    dists[i] = __builtin_inff();
+  }
+}
+
+// ---------------------------------------------------------------- dense exact
+
+// Every pair, all 21 points, both orders, no early exit: the exact stage run
+// on the whole N x M product.  Each lane keeps FPL fibers (63 floats each) in
+// registers; the centroid record is wave-uniform and arrives through scalar
+// loads, so the inner loop is pure VALU work (3 differences, 1 product,
+// 2 FMAs and a max per point distance).  The argmin stays in registers: the
+// centroid loop runs in increasing index order and a strictly smaller D
+// replaces the best, so equal distances keep the lower index.
+template <int FPL>
+__global__ __launch_bounds__(256) void dense_kernel(const float* __restrict__ fibers, int64_t n,
+                                                    const float* __restrict__ cprep, int32_t m,
+                                                    const int32_t* __restrict__ bid,
+                                                    int32_t* __restrict__ labels,
+                                                    float* __restrict__ dists) {
+  const int64_t base = ((int64_t)blockIdx.x * blockDim.x) * FPL + threadIdx.x;
+  float a[FPL][NF];
+  float best[FPL];
+  int32_t bc[FPL];
+#pragma unroll
+  for (int k = 0; k < FPL; ++k) {
+    const int64_t f = base + (int64_t)k * blockDim.x;
+    const float* src = fibers + (f < n ? f : 0) * NF;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) a[k][j] = src[j];
+    best[k] = 0.0f;
+    bc[k] = -1;
+  }
+  for (int32_t c = 0; c < m; ++c) {
+    const float* b = cprep + (size_t)c * CREC;
+    const float t2 = b[NF];
+#pragma unroll
+    for (int k = 0; k < FPL; ++k) {
+      float mc = d2(a[k][3 * CTR], a[k][3 * CTR + 1], a[k][3 * CTR + 2], b[3 * CTR],
+                    b[3 * CTR + 1], b[3 * CTR + 2]);
+      float md = mc, mi = mc;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (i == CTR) continue;
+        const int j = NP - 1 - i;
+        float x = d2(a[k][3 * i], a[k][3 * i + 1], a[k][3 * i + 2], b[3 * i], b[3 * i + 1],
+                     b[3 * i + 2]);
+        float y = d2(a[k][3 * i], a[k][3 * i + 1], a[k][3 * i + 2], b[3 * j], b[3 * j + 1],
+                     b[3 * j + 2]);
+        md = fmaxf(md, x);
+        mi = fmaxf(mi, y);
+      }
+      const float D = fminf(md, mi);
+      const bool take = D <= t2 && (bc[k] < 0 || D < best[k]);
+      best[k] = take ? D : best[k];
+      bc[k] = take ? c : bc[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < FPL; ++k) {
+    const int64_t f = base + (int64_t)k * blockDim.x;
+    if (f < n) {
+      uint64_t key = bc[k] < 0 ? NO_KEY : make_key(best[k], (uint32_t)bc[k]);
+      write_result(key, bid, labels + f, dists + f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- plain pass
+
+// The paper's test1 on every pair, fused with the rest of the method.
+// Each wave owns 64 * FPL consecutive fibers (lane l, slot k*64 + l) and keeps
+// their center points in registers.  For every centroid (wave-uniform, a
+// 16-byte scalar load of center + T2) each lane evaluates the center distance
+// of its FPL fibers.  Survivors are rare; when a wave has any, it appends
+// them to its LDS queue with a ballot + prefix count.  A nearly full queue is
+// drained by running tests 2-4 and the full metric with one queued pair per
+// lane (exact_pair); accepted pairs are merged into per-fiber 64-bit
+// (D, centroid) keys in LDS with an atomic minimum, which makes the result
+// independent of drain order.  Memory stays O(N + M): no N x M buffer exists.
+template <int FPL, int QCAP, bool STATS>
+__global__ __launch_bounds__(256) void plain_kernel(const float* __restrict__ fibers, int64_t n,
+                                                    const float4* __restrict__ ccen,
+                                                    const float* __restrict__ cprep, int32_t m,
+                                                    const int32_t* __restrict__ bid,
+                                                    int32_t* __restrict__ labels,
+                                                    float* __restrict__ dists,
+                                                    unsigned long long* __restrict__ counters) {
+  static_assert(64 * FPL <= 256, "slot must fit 8 bits");
+  static_assert(QCAP >= 2 * 64 * FPL, "queue must hold two centroids' worth");
+  constexpr int WAVES = 4;
+  __shared__ uint32_t s_queue[WAVES][QCAP];
+  __shared__ uint64_t s_keys[WAVES][64 * FPL];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)blockIdx.x * WAVES + wave) * (64 * FPL);
+  WaveQueue wq{s_queue[wave], s_keys[wave]};
+  StageCounts sc{counters};
+
+  float ax[FPL], ay[FPL], az[FPL];
+#pragma unroll
+  for (int k = 0; k < FPL; ++k) {
+    const int64_t f = wbase + k * 64 + lane;
+    if (f < n) {
+      const float* p = fibers + f * NF + 3 * CTR;
+      ax[k] = p[0];
+      ay[k] = p[1];
+      az[k] = p[2];
+    } else {
+      // a NaN center fails every comparison, so padding lanes never survive
+      ax[k] = ay[k] = az[k] = __builtin_nanf("");
+    }
+    wq.keys[k * 64 + lane] = NO_KEY;
+  }
+  const float* fib_base = fibers + (wbase < n ? wbase : 0) * NF;
+
+  uint32_t qn = 0;
+  for (int32_t c = 0; c < m; ++c) {
+    const float4 q = ccen[c];
+    uint64_t msk[FPL];
+    uint64_t any = 0;
+#pragma unroll
+    for (int k = 0; k < FPL; ++k) {
+      msk[k] = __ballot(d2(ax[k], ay[k], az[k], q.x, q.y, q.z) <= q.w);
+      any |= msk[k];
+    }
+    if (any) {
+#pragma unroll
+      for (int k = 0; k < FPL; ++k)
+        if (msk[k]) queue_push(wq, qn, msk[k], ((uint32_t)c << 8) | (uint32_t)(k * 64 + lane));
+      if (qn > (uint32_t)(QCAP - 64 * FPL)) {
+        queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
+        qn = 0;
+      }
+    }
+  }
+  queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
+
+#pragma unroll
+  for (int k = 0; k < FPL; ++k) {
+    const int64_t f = wbase + k * 64 + lane;
+    if (f < n) write_result(wq.keys[k * 64 + lane], bid, labels + f, dists + f);
+  }
+}
+
+// Survivors of the center test as (fiber, centroid) pairs (diagnostics).
+__global__ __launch_bounds__(256) void plain_pairs_kernel(const float* __restrict__ fibers,
+                                                          int64_t n,
+                                                          const float4* __restrict__ ccen,
+                                                          int32_t m, int32_t* __restrict__ pairs,
+                                                          int64_t cap,
+                                                          unsigned long long* __restrict__ count) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const float* p = fibers + f * NF + 3 * CTR;
+  const float x = p[0], y = p[1], z = p[2];
+  for (int32_t c = 0; c < m; ++c) {
+    const float4 q = ccen[c];
+    if (d2(x, y, z, q.x, q.y, q.z) <= q.w) {
+      unsigned long long k = atomicAdd(count, 1ull);
+      if ((int64_t)k < cap) {
+        pairs[2 * k] = (int32_t)f;
+        pairs[2 * k + 1] = c;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const float* thr,
+                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out,
+                      unsigned int* flags, hipStream_t s) {
+  if (m > 0) {
+    prep_atlas_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cen, m, bid, thr, nb, cprep,
+                                                                   ccen, bid_out, flags);
+  }
+  if (nb > 0) check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_check_finite(const float* v, int64_t count, unsigned int* flags, hipStream_t s) {
+  if (count <= 0) return 0;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  check_finite_kernel<<<(unsigned)blocks, 256, 0, s>>>(v, count, flags);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {
+  if (n > 0) fill_u64_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_empty(int64_t n, int32_t* labels, float* dists, hipStream_t s) {
+  if (n > 0) fill_empty_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, labels, dists);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_dense(const float* fibers, int64_t n, const float* cprep, int32_t m,
+                 const int32_t* bid, int32_t* labels, float* dists, int cfg, hipStream_t s) {
+  // cfg 1: one fiber per lane; cfg 2: two fibers per lane
+  const int fpl = cfg == 2 ? 2 : 1;
+  const int64_t per_block = 256 * fpl;
+  const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
+  if (fpl == 2)
+    dense_kernel<2><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists);
+  else
+    dense_kernel<1><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int FPL>
+static void plain_launch(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
+                         int32_t m, const int32_t* bid, int32_t* labels, float* dists,
+                         unsigned long long* counters, hipStream_t s) {
+  constexpr int per_block = 4 * 64 * FPL;
+  const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
+  constexpr int QCAP = 512;
+  if (counters)
+    plain_kernel<FPL, QCAP, true><<<blocks, 256, 0, s>>>(fibers, n, ccen, cprep, m, bid, labels,
+                                                         dists, counters);
+  else
+    plain_kernel<FPL, QCAP, false><<<blocks, 256, 0, s>>>(fibers, n, ccen, cprep, m, bid, labels,
+                                                          dists, counters);
+}
+
+int plain_default_cfg(int64_t n) {
+  // enough waves to fill 256 CUs x 4 SIMDs several times over
+  const int64_t want_waves = 256 * 4 * 8;
+  if (n >= want_waves * 64 * 4) return 4;
+  if (n >= want_waves * 64 * 2) return 2;
+  return 1;
+}
+
+int launch_plain(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
+                 int32_t m, const int32_t* bid, int32_t* labels, float* dists,
+                 unsigned long long* counters, int cfg, hipStream_t s) {
+  if (cfg <= 0) cfg = plain_default_cfg(n);
+  switch (cfg) {
+    case 1: plain_launch<1>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
+    case 2: plain_launch<2>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
+    case 4: plain_launch<4>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
+    default: return -2;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32_t m,
+                       int32_t* pairs, int64_t cap, unsigned long long* count, hipStream_t s) {
+  plain_pairs_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fibers, n, ccen, m, pairs, cap,
+                                                                 count);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace seg

@@ -1,0 +1,253 @@
+"""Python binding of libseg.so (argument marshalling only).
+
+Every step of the segmentation runs in the library's HIP kernels; this module
+passes device pointers, sizes and the current HIP stream through ctypes and
+raises when the library reports an error.  PyTorch is used only to own device
+memory and to name the stream.  There is no CPU fallback: if the library is
+missing, or a tensor is not on the GPU, the call fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libseg.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "seg.h")
+
+# seg_mode
+DENSE = 0
+PLAIN = 1
+PREFILTER_BF16 = 2
+PREFILTER_FP16 = 3
+PREFILTER_FP8 = 4
+PREFILTER_BF16_ORIENTED = 5
+
+MODES = {
+    "dense": DENSE,
+    "plain": PLAIN,
+    "bf16": PREFILTER_BF16,
+    "fp16": PREFILTER_FP16,
+    "fp8": PREFILTER_FP8,
+    "bf16_oriented": PREFILTER_BF16_ORIENTED,
+}
+
+STATUS = {0: "SEG_OK", -1: "SEG_EINVAL", -2: "SEG_EBUNDLE", -3: "SEG_ENONFINITE",
+          -4: "SEG_EHIP", -5: "SEG_ENOMEM", -6: "SEG_ERANGE", -7: "SEG_EMODE"}
+
+
+class SegError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("collect_stats", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("pairs", "filter_pass", "test2_pass", "test3_pass", "accepted", "labelled",
+                 "drains")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libseg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1912_11494_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        i32 = ctypes.c_int32
+        L.seg_segment.argtypes = [P, i64, P, i64, P, P, i32, P, P, ctypes.POINTER(Options), P]
+        L.seg_segment.restype = ctypes.c_int
+        L.seg_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.seg_last_error.restype = ctypes.c_char_p
+        L.seg_version.restype = ctypes.c_int
+        L.seg_atlas_create.argtypes = [P, i64, P, P, i32, P, ctypes.POINTER(P)]
+        L.seg_atlas_create.restype = ctypes.c_int
+        L.seg_atlas_destroy.argtypes = [P]
+        L.seg_atlas_size.argtypes = [P]
+        L.seg_atlas_size.restype = i64
+        L.seg_segment_atlas.argtypes = [P, P, i64, P, P, ctypes.POINTER(Options), P]
+        L.seg_segment_atlas.restype = ctypes.c_int
+        L.seg_segment_batch.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(P),
+                                        ctypes.POINTER(i64), i32, ctypes.POINTER(P),
+                                        ctypes.POINTER(P), ctypes.POINTER(Options), P]
+        L.seg_segment_batch.restype = ctypes.c_int
+        L.seg_filter_pairs.argtypes = [P, i64, P, i64, P, P, i32, i32, P, i64,
+                                       ctypes.POINTER(i64), P]
+        L.seg_filter_pairs.restype = ctypes.c_int
+        L.seg_query_stats.argtypes = [ctypes.POINTER(Stats)]
+        L.seg_query_stats.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions() -> List[str]:
+    """Names of the functions declared in include/seg.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(seg_[a-z_]+)\s*\(", txt)))
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SegError(rc, lib().seg_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, shape_tail=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} must have shape [*, {', '.join(map(str, shape_tail))}]")
+    return t
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        if mode not in MODES:
+            raise ValueError(f"unknown mode {mode!r}; one of {sorted(MODES)}")
+        return MODES[mode]
+    return int(mode)
+
+
+def options(mode="plain", validate=False, tile=0, stats=False) -> Options:
+    return Options(_mode(mode), int(bool(validate)), int(tile), int(bool(stats)))
+
+
+def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: torch.Tensor,
+            bundle_thresholds: torch.Tensor, mode="plain", validate=False, tile=0, stats=False,
+            out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+            stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """labels (int32 [N]) and dists (float32 [N]) of each fiber; see include/seg.h."""
+    _dev(fibers, torch.float32, (21, 3), "fibers")
+    _dev(centroids, torch.float32, (21, 3), "centroids")
+    _dev(centroid_bundle_id, torch.int32, None, "centroid_bundle_id")
+    _dev(bundle_thresholds, torch.float32, None, "bundle_thresholds")
+    n = fibers.shape[0]
+    if out is None:
+        labels = torch.empty(n, dtype=torch.int32, device=fibers.device)
+        dists = torch.empty(n, dtype=torch.float32, device=fibers.device)
+    else:
+        labels, dists = out
+        _dev(labels, torch.int32, None, "labels")
+        _dev(dists, torch.float32, None, "dists")
+    opt = options(mode, validate, tile, stats)
+    rc = lib().seg_segment(fibers.data_ptr(), n, centroids.data_ptr(), centroids.shape[0],
+                           centroid_bundle_id.data_ptr(), bundle_thresholds.data_ptr(),
+                           bundle_thresholds.shape[0], labels.data_ptr(), dists.data_ptr(),
+                           ctypes.byref(opt), _stream(stream))
+    _check(rc)
+    return labels, dists
+
+
+def query_stats() -> dict:
+    st = Stats()
+    _check(lib().seg_query_stats(ctypes.byref(st)))
+    return st.as_dict()
+
+
+def filter_pairs(fibers, centroids, centroid_bundle_id, bundle_thresholds, mode="plain",
+                 capacity: int = 1 << 20, stream=None) -> torch.Tensor:
+    """Survivors of the first cut of `mode` as an int32 [K, 2] (fiber, centroid) tensor."""
+    _dev(fibers, torch.float32, (21, 3), "fibers")
+    _dev(centroids, torch.float32, (21, 3), "centroids")
+    pairs = torch.empty((capacity, 2), dtype=torch.int32, device=fibers.device)
+    cnt = ctypes.c_int64(0)
+    rc = lib().seg_filter_pairs(fibers.data_ptr(), fibers.shape[0], centroids.data_ptr(),
+                                centroids.shape[0], centroid_bundle_id.data_ptr(),
+                                bundle_thresholds.data_ptr(), bundle_thresholds.shape[0],
+                                _mode(mode), pairs.data_ptr(), capacity, ctypes.byref(cnt),
+                                _stream(stream))
+    _check(rc)
+    if cnt.value > capacity:
+        raise SegError(-5, f"{cnt.value} survivors exceed capacity {capacity}")
+    return pairs[:cnt.value]
+
+
+class Atlas:
+    """A prepared atlas held by the library (seg_atlas_create / seg_atlas_destroy)."""
+
+    def __init__(self, centroids, centroid_bundle_id, bundle_thresholds, stream=None):
+        _dev(centroids, torch.float32, (21, 3), "centroids")
+        _dev(centroid_bundle_id, torch.int32, None, "centroid_bundle_id")
+        _dev(bundle_thresholds, torch.float32, None, "bundle_thresholds")
+        h = ctypes.c_void_p()
+        rc = lib().seg_atlas_create(centroids.data_ptr(), centroids.shape[0],
+                                    centroid_bundle_id.data_ptr(), bundle_thresholds.data_ptr(),
+                                    bundle_thresholds.shape[0], _stream(stream), ctypes.byref(h))
+        _check(rc)
+        self.handle = h
+        self.device = centroids.device
+
+    def __len__(self):
+        return int(lib().seg_atlas_size(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().seg_atlas_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def segment(self, fibers, mode="plain", validate=False, tile=0, stats=False, stream=None):
+        _dev(fibers, torch.float32, (21, 3), "fibers")
+        n = fibers.shape[0]
+        labels = torch.empty(n, dtype=torch.int32, device=fibers.device)
+        dists = torch.empty(n, dtype=torch.float32, device=fibers.device)
+        opt = options(mode, validate, tile, stats)
+        rc = lib().seg_segment_atlas(self.handle, fibers.data_ptr(), n, labels.data_ptr(),
+                                     dists.data_ptr(), ctypes.byref(opt), _stream(stream))
+        _check(rc)
+        return labels, dists
+
+
+def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mode="bf16",
+                  tile=0, outs=None, stream=None):
+    """Labels/dists of every (subject, atlas) pair: a list over subjects of lists over atlases."""
+    na, ns = len(atlases), len(subjects)
+    for f in subjects:
+        _dev(f, torch.float32, (21, 3), "fibers")
+    if outs is None:
+        outs = [[(torch.empty(f.shape[0], dtype=torch.int32, device=f.device),
+                  torch.empty(f.shape[0], dtype=torch.float32, device=f.device))
+                 for _ in range(na)] for f in subjects]
+    P = ctypes.c_void_p
+    ah = (P * max(na, 1))(*[a.handle.value for a in atlases])
+    fp = (P * max(ns, 1))(*[f.data_ptr() for f in subjects])
+    nf = (ctypes.c_int64 * max(ns, 1))(*[f.shape[0] for f in subjects])
+    lp = (P * max(ns * na, 1))(*[outs[s][a][0].data_ptr() for s in range(ns) for a in range(na)])
+    dp = (P * max(ns * na, 1))(*[outs[s][a][1].data_ptr() for s in range(ns) for a in range(na)])
+    opt = options(mode, False, tile, False)
+    rc = lib().seg_segment_batch(ah, na, fp, nf, ns, lp, dp, ctypes.byref(opt), _stream(stream))
+    _check(rc)
+    return outs
