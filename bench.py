@@ -1,0 +1,293 @@
+#!/usr/bin/env python
+"""Benchmark of the segmentation hot path on one MI355X.
+
+One step = one pass of the whole path over one subject resident in HBM:
+atlas preparation, the first cut (center test or MFMA prefilter), the exact
+float32 stage on survivors and the per-fiber argmin / label write.  The
+workload is the paper-scale subject: 4,145,000 fibers against 10,000
+centroids (100 bundles x 100), 21 points of float32 each, synthetic.
+
+    python bench.py [--steps K] [--warmup W] [--mode bf16|plain|dense|...]
+
+Prints one JSON line.  `value` is pairs/s of the headline mode (N*M per
+step); every other compared mode is reported under "modes".  The dominant
+kernel of the headline mode is timed live with HIP events recorded by the
+library right around its launch (seg_options.profile_events), on the stream
+the kernel runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fiber-centroid pairs/s and fibers/s at 4.1M x 10k; prefilter vs plain speedup"
+PEAK_FP32 = 157.3   # TFLOP/s, MI355X vector FP32 (256 CU x 4 SIMD x 32 lanes x FMA x 2.4 GHz)
+PEAK_BF16 = 2500.0  # TFLOP/s dense MFMA
+PEAK_FP8 = 5000.0
+PEAK_HBM = 8000.0   # GB/s
+WORKLOADS = {
+    1: "20,000 fibers x 800 centroids (40 bundles x 20), 21 pts fp32",
+    2: "1,000,000 fibers x 3,600 centroids (36 bundles x 100), 21 pts fp32",
+    3: "4,145,000 fibers x 10,000 centroids (100 bundles x 100, 20-80 mm), 21 pts fp32",
+    4: "10,000,000 fibers x 20,000 centroids (200 bundles x 100), 21 pts fp32",
+}
+KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
+                  "paper_1912_11494_amd/csrc/seg_kernels.hip",
+                  "paper_1912_11494_amd/csrc/seg_prefilter.hip"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Hip:
+    """hipEvent_* through ctypes (the library is HIP; so are these events)."""
+
+    def __init__(self):
+        self.L = ctypes.CDLL("libamdhip64.so")
+        self.L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.L.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.L.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                               ctypes.c_void_p]
+        self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def event(self):
+        e = ctypes.c_void_p()
+        assert self.L.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def record(self, e, stream):
+        assert self.L.hipEventRecord(e, stream) == 0
+
+    def elapsed(self, a, b) -> float:
+        ms = ctypes.c_float()
+        assert self.L.hipEventSynchronize(b) == 0
+        assert self.L.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return float(ms.value)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is absent or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    n = f.shape[0]
+    out = (torch.empty(n, dtype=torch.int32, device=f.device),
+           torch.empty(n, dtype=torch.float32, device=f.device))
+    for _ in range(warmup):
+        P.segment(f, c, b, t, mode=mode, tile=tile, out=out)
+    torch.cuda.synchronize()
+    pairs = [(hip.event(), hip.event()) for _ in range(steps)]
+    arrs = [(ctypes.c_void_p * 2)(a.value, z.value) for a, z in pairs]
+    e0, e1 = hip.event(), hip.event()
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    hip.record(e0, sh)
+    for k in range(steps):
+        P.segment(f, c, b, t, mode=mode, tile=tile, out=out, events=ctypes.addressof(arrs[k]))
+    hip.record(e1, sh)
+    torch.cuda.synchronize()
+    h1 = time.perf_counter()
+    total_ms = hip.elapsed(e0, e1)
+    kern = [hip.elapsed(a, z) for a, z in pairs]
+    return {
+        "ms_per_step": total_ms / steps,
+        "host_ms_per_step": (h1 - h0) * 1e3 / steps,
+        "kernel_ms": sum(kern) / steps,
+        "kernel_ms_min": min(kern),
+        "kernel_ms_max": max(kern),
+    }, out
+
+
+def alg_flops(mode, st, n, m, kfeat=None):
+    """Algorithmic FLOPs of the dominant kernel per launch (8 FLOP per point
+    distance: 3 sub, 3 mul, 2 add)."""
+    if mode == "dense":
+        return 328.0 * n * m  # 41 distinct point distances per pair
+    exact = 32.0 * st["filter_pass"] + 64.0 * st["test2_pass"] + 224.0 * st["test3_pass"]
+    if mode == "plain":
+        return 8.0 * n * m + exact
+    return 2.0 * kfeat * n * m  # prefilter product (the exact stage is reported apart)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--mode", default=None, help="headline mode (default: fastest built)")
+    ap.add_argument("--compare", default="plain,dense,bf16,fp16,bf16_oriented,fp8")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="fibers of the workload the CPU oracle is timed on")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "this library segments one subject per GPU and has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import synth
+
+    cfg = args.config
+    at = synth.config_atlases(cfg)[0]
+    subj = synth.config_subjects(cfg)[0]
+    t0 = time.time()
+    fib = synth.make_fibers([at], subj, synth.fibers.config_seed(cfg))
+    log(f"generated config {cfg}: {fib.shape[0]} fibers x {at.n_centroids} centroids "
+        f"in {time.time() - t0:.1f}s")
+
+    import torch
+
+    import paper_1912_11494_amd as P
+
+    hip = Hip()
+    d = torch.device("cuda:0")
+    f = torch.from_numpy(fib).to(d)
+    c = torch.from_numpy(at.centroids).to(d)
+    b = torch.from_numpy(at.bundle_id).to(d)
+    t = torch.from_numpy(at.thresholds).to(d)
+    N, M = fib.shape[0], at.n_centroids
+
+    modes = {}
+    outs = {}
+    for mode in [m for m in args.compare.split(",") if m]:
+        try:
+            P.segment(f, c, b, t, mode=mode)
+        except P.SegError as e:
+            log(f"mode {mode}: not available ({e})")
+            continue
+        torch.cuda.synchronize()
+        r, out = time_mode(P, hip, f, c, b, t, mode, args.steps, args.warmup)
+        P.segment(f, c, b, t, mode=mode, stats=True)
+        st = P.query_stats()
+        r["pairs_per_s"] = N * M / (r["ms_per_step"] * 1e-3)
+        r["fibers_per_s"] = N / (r["ms_per_step"] * 1e-3)
+        r["survivors_per_fiber"] = st["filter_pass"] / N if mode != "dense" else None
+        r["accepted_pairs"] = st["accepted"] if mode != "dense" else None
+        r["stats"] = st
+        modes[mode] = r
+        outs[mode] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+        log(f"mode {mode}: {r['ms_per_step']:.3f} ms/step, kernel {r['kernel_ms']:.3f} ms, "
+            f"{r['pairs_per_s']:.3e} pairs/s")
+
+    if not modes:
+        raise SystemExit("no mode could run")
+    ref = outs.get("plain") or next(iter(outs.values()))
+    diffs = {m: int((o[0] != ref[0]).sum()) for m, o in outs.items()}
+    ddiffs = {m: int((o[1] != ref[1]).sum()) for m, o in outs.items()}
+
+    head = args.mode
+    if head is None:
+        prod = [m for m in ("bf16", "fp16", "plain") if m in modes]
+        head = min(prod, key=lambda m: modes[m]["ms_per_step"])
+    r = modes[head]
+    kfeat = r["stats"].get("kfeat") if isinstance(r.get("stats"), dict) else None
+    if head in ("dense", "plain"):
+        bound, peak, kname = "alu", PEAK_FP32, f"{head}_kernel"
+        ach = alg_flops(head, r["stats"], N, M) / (r["kernel_ms"] * 1e-3) / 1e12
+        dtype = "f32"
+    else:
+        bound, kname = "mfma", "prefilter_kernel"
+        peak = PEAK_FP8 if head == "fp8" else PEAK_BF16
+        kf = {"bf16": 16, "fp16": 16, "fp8": 16, "bf16_oriented": 128}.get(head, 16)
+        ach = alg_flops(head, r["stats"], N, M, kf) / (r["kernel_ms"] * 1e-3) / 1e12
+        dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head, "bf16+f32")
+    roofline = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": traffic_for(kname), "kernel": kname,
+                "kernel_ms": r["kernel_ms"]}
+    if "dense" in modes:
+        dm = modes["dense"]
+        a_d = alg_flops("dense", None, N, M) / (dm["kernel_ms"] * 1e-3) / 1e12
+        roofline["exact_stage_dense"] = {"achieved": a_d, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                                         "frac": a_d / PEAK_FP32, "kernel_ms": dm["kernel_ms"]}
+
+    cpu = None
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle
+
+        ns = min(args.cpu_sample, N)
+        thr = oracle.get().max_threads()
+        h0 = time.perf_counter()
+        l_cpu, d_cpu, _ = oracle.segment_f32(fib[:ns], at.centroids, at.bundle_id, at.thresholds,
+                                            mode=oracle.CUT, threads=thr)
+        dt = time.perf_counter() - h0
+        cpu = {"value": ns * M / dt, "unit": "pairs/s", "cores": thr, "kind": "oracle",
+               "sample": f"first {ns:,} of {N:,} fibers x all {M:,} centroids, float32, the "
+                         f"paper's progressive discard (tests 1-4), OpenMP {thr} threads; "
+                         f"{dt:.1f} s",
+               "fibers_per_s": ns / dt,
+               "labels_match_gpu": bool(np.array_equal(l_cpu, ref[0][:ns]))}
+        log(f"cpu oracle: {ns} fibers in {dt:.1f}s ({cpu['value']:.3e} pairs/s, {thr} threads)")
+
+    plain_ms = modes.get("plain", {}).get("ms_per_step")
+    speed = {m: plain_ms / modes[m]["ms_per_step"] for m in modes
+             if plain_ms and m not in ("plain", "dense")}
+    line = {
+        "metric": METRIC,
+        "value": r["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"config {cfg}: {WORKLOADS[cfg]}", "fibers": N, "centroids": M,
+                   "bundles": at.n_bundles, "mode": head},
+        "fibers_per_s": r["fibers_per_s"],
+        "prefilter_vs_plain_speedup": speed,
+        "label_diffs_vs_plain": diffs,
+        "dist_diffs_vs_plain": ddiffs,
+        "modes": {m: {k: v for k, v in x.items() if k != "stats"} | {"stats": x["stats"]}
+                  for m, x in modes.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

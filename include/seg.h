@@ -85,6 +85,11 @@ typedef struct seg_options {
                             k > 0: kernel configuration k of the mode */
   int32_t collect_stats; /* 1: count survivors per stage (read with
                             seg_query_stats; adds atomics, not for timing) */
+  void* profile_events;  /* optional host pointer to two hipEvent_t: the
+                            library records [0] right before and [1] right
+                            after the launch of the mode's dominant kernel
+                            (on `stream`), so a caller can time that kernel
+                            alone; NULL = no events */
 } seg_options;
 
 typedef struct seg_stats {
@@ -98,7 +103,8 @@ typedef struct seg_stats {
   int64_t drains;          /* survivor-queue drains (wave level) */
 } seg_stats;
 
-/* Default options (mode SEG_PLAIN, no validation, library tiles, no stats). */
+/* Default options (mode SEG_PLAIN, no validation, library tiles, no stats,
+   no profiling events). */
 void seg_default_options(seg_options* opt);
 
 /*

@@ -177,18 +177,23 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
   if (counters && seg::launch_fill_u64(counters, seg::NCOUNTERS, 0ull, s))
     return hip_fail(hipGetLastError(), "counter reset");
   const int32_t m = (int32_t)ab.m;
+  hipEvent_t* ev = (hipEvent_t*)o.profile_events;
   int rc = 0;
   switch (o.mode) {
     case SEG_DENSE:
+      if (ev) HIP_TRY(hipEventRecord(ev[0], s));
       rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, o.tile, s);
+      if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     case SEG_PLAIN:
+      if (ev) HIP_TRY(hipEventRecord(ev[0], s));
       rc = seg::launch_plain(fibers, n, ab.ccen, ab.cprep, m, ab.bid, labels, dists, counters,
                              o.tile, s);
+      if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     default:
       rc = seg::run_prefilter(o.mode, o.tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
-                              dists, counters, sc->pre, s);
+                              dists, counters, sc->pre, ev, s);
       if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
       break;
   }
@@ -221,6 +226,7 @@ void seg_default_options(seg_options* opt) {
   opt->validate = 0;
   opt->tile = 0;
   opt->collect_stats = 0;
+  opt->profile_events = nullptr;
 }
 
 const char* seg_last_error(void) { return t_err.c_str(); }

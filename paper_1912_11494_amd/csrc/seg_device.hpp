@@ -160,7 +160,7 @@ __device__ __forceinline__ void queue_push(WaveQueue wq, uint32_t& n, uint64_t m
 // per-fiber argmin keys.  `fib_base` points at the wave's first fiber record;
 // `cprep` holds the prepared centroid records (63 coordinates + T2).
 template <bool STATS>
-__device__ __forceinline__ void queue_drain(WaveQueue wq, uint32_t n,
+__device__ __forceinline__ void queue_drain_body(WaveQueue wq, uint32_t n,
                                             const float* __restrict__ fib_base,
                                             const float* __restrict__ cprep, StageCounts sc) {
   const uint32_t lane = lane_id();
@@ -179,6 +179,23 @@ __device__ __forceinline__ void queue_drain(WaveQueue wq, uint32_t n,
                                 sc);
     if (ok) atomicMin((unsigned long long*)&wq.keys[slot], (unsigned long long)make_key(D, c));
   }
+}
+
+template <bool STATS>
+__device__ __forceinline__ void queue_drain(WaveQueue wq, uint32_t n,
+                                            const float* __restrict__ fib_base,
+                                            const float* __restrict__ cprep, StageCounts sc) {
+  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc);
+}
+
+// The same as a real call: drains are rare, and keeping the exact stage out
+// of line lets a caller with many live registers (the MFMA accumulators of
+// the prefilter) not reserve the exact stage's registers on top of its own.
+template <bool STATS>
+__device__ __noinline__ void queue_drain_call(WaveQueue wq, uint32_t n,
+                                              const float* __restrict__ fib_base,
+                                              const float* __restrict__ cprep, StageCounts sc) {
+  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc);
 }
 
 // Final write of one fiber from its argmin key.

@@ -58,7 +58,8 @@ int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32
 // unsupported mode or tile, -3 on a failed allocation.
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
-                  float* dists, unsigned long long* counters, PrefilterBuf& pb, hipStream_t s);
+                  float* dists, unsigned long long* counters, PrefilterBuf& pb, hipEvent_t* ev,
+                  hipStream_t s);
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,
                     unsigned long long* count, PrefilterBuf& pb, hipStream_t s);

@@ -28,7 +28,14 @@ __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict
                                                          int32_t* __restrict__ bid_out,
                                                          unsigned int* __restrict__ flags) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
+  if (c >= m) {
+    // padding up to a multiple of 8: a center test that never passes
+    if (c < ((m + 7) & ~(int64_t)7)) {
+      ccen[c] = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+      bid_out[c] = -1;
+    }
+    return;
+  }
   const float* src = cen + c * NF;
   float* dst = cprep + c * CREC;
   const int32_t b = bid[c];
@@ -194,23 +201,40 @@ __global__ __launch_bounds__(256) void plain_kernel(const float* __restrict__ fi
   }
   const float* fib_base = fibers + (wbase < n ? wbase : 0) * NF;
 
+  // Centroids in groups of 4 (one 64-byte scalar burst); ccen is padded to a
+  // multiple of 8 with entries that never pass.  The next group is loaded
+  // while the current one is evaluated.
+  const int32_t m4 = (m + 3) & ~3;
   uint32_t qn = 0;
-  for (int32_t c = 0; c < m; ++c) {
-    const float4 q = ccen[c];
-    uint64_t msk[FPL];
+  float4 n0 = ccen[0], n1 = ccen[1], n2 = ccen[2], n3 = ccen[3];
+  for (int32_t c0 = 0; c0 < m4; c0 += 4) {
+    const float4 q[4] = {n0, n1, n2, n3};
+    const int32_t cn = c0 + 4 < m4 ? c0 + 4 : c0;
+    n0 = ccen[cn];
+    n1 = ccen[cn + 1];
+    n2 = ccen[cn + 2];
+    n3 = ccen[cn + 3];
+    uint64_t msk[4][FPL];
     uint64_t any = 0;
 #pragma unroll
-    for (int k = 0; k < FPL; ++k) {
-      msk[k] = __ballot(d2(ax[k], ay[k], az[k], q.x, q.y, q.z) <= q.w);
-      any |= msk[k];
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int k = 0; k < FPL; ++k) {
+        msk[u][k] = __ballot(d2(ax[k], ay[k], az[k], q[u].x, q[u].y, q[u].z) <= q[u].w);
+        any |= msk[u][k];
+      }
     }
     if (any) {
 #pragma unroll
-      for (int k = 0; k < FPL; ++k)
-        if (msk[k]) queue_push(wq, qn, msk[k], ((uint32_t)c << 8) | (uint32_t)(k * 64 + lane));
-      if (qn > (uint32_t)(QCAP - 64 * FPL)) {
-        queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
-        qn = 0;
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t c = (uint32_t)(c0 + u);
+#pragma unroll
+        for (int k = 0; k < FPL; ++k)
+          if (msk[u][k]) queue_push(wq, qn, msk[u][k], (c << 8) | (uint32_t)(k * 64 + lane));
+        if (qn > (uint32_t)(QCAP - 64 * FPL)) {
+          queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
+          qn = 0;
+        }
       }
     }
   }
@@ -252,8 +276,9 @@ int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const flo
                       int32_t nb, float* cprep, float4* ccen, int32_t* bid_out,
                       unsigned int* flags, hipStream_t s) {
   if (m > 0) {
-    prep_atlas_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cen, m, bid, thr, nb, cprep,
-                                                                   ccen, bid_out, flags);
+    const int64_t mp = (m + 7) & ~(int64_t)7;
+    prep_atlas_kernel<<<(unsigned)((mp + 255) / 256), 256, 0, s>>>(cen, m, bid, thr, nb, cprep,
+                                                                    ccen, bid_out, flags);
   }
   if (nb > 0) check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -48,7 +48,8 @@ class SegError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("collect_stats", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
+                ("profile_events", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -136,14 +137,15 @@ def _mode(mode) -> int:
     return int(mode)
 
 
-def options(mode="plain", validate=False, tile=0, stats=False) -> Options:
-    return Options(_mode(mode), int(bool(validate)), int(tile), int(bool(stats)))
+def options(mode="plain", validate=False, tile=0, stats=False, events=None) -> Options:
+    """seg_options; `events` is an optional address of two hipEvent_t."""
+    return Options(_mode(mode), int(bool(validate)), int(tile), int(bool(stats)), events)
 
 
 def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: torch.Tensor,
             bundle_thresholds: torch.Tensor, mode="plain", validate=False, tile=0, stats=False,
-            out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
-            stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+            out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, stream=None,
+            events=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """labels (int32 [N]) and dists (float32 [N]) of each fiber; see include/seg.h."""
     _dev(fibers, torch.float32, (21, 3), "fibers")
     _dev(centroids, torch.float32, (21, 3), "centroids")
@@ -157,7 +159,7 @@ def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: t
         labels, dists = out
         _dev(labels, torch.int32, None, "labels")
         _dev(dists, torch.float32, None, "dists")
-    opt = options(mode, validate, tile, stats)
+    opt = options(mode, validate, tile, stats, events)
     rc = lib().seg_segment(fibers.data_ptr(), n, centroids.data_ptr(), centroids.shape[0],
                            centroid_bundle_id.data_ptr(), bundle_thresholds.data_ptr(),
                            bundle_thresholds.shape[0], labels.data_ptr(), dists.data_ptr(),
@@ -219,12 +221,16 @@ class Atlas:
         except Exception:
             pass
 
-    def segment(self, fibers, mode="plain", validate=False, tile=0, stats=False, stream=None):
+    def segment(self, fibers, mode="plain", validate=False, tile=0, stats=False, stream=None,
+                events=None, out=None):
         _dev(fibers, torch.float32, (21, 3), "fibers")
         n = fibers.shape[0]
-        labels = torch.empty(n, dtype=torch.int32, device=fibers.device)
-        dists = torch.empty(n, dtype=torch.float32, device=fibers.device)
-        opt = options(mode, validate, tile, stats)
+        if out is None:
+            labels = torch.empty(n, dtype=torch.int32, device=fibers.device)
+            dists = torch.empty(n, dtype=torch.float32, device=fibers.device)
+        else:
+            labels, dists = out
+        opt = options(mode, validate, tile, stats, events)
         rc = lib().seg_segment_atlas(self.handle, fibers.data_ptr(), n, labels.data_ptr(),
                                      dists.data_ptr(), ctypes.byref(opt), _stream(stream))
         _check(rc)
@@ -247,7 +253,7 @@ def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mo
     nf = (ctypes.c_int64 * max(ns, 1))(*[f.shape[0] for f in subjects])
     lp = (P * max(ns * na, 1))(*[outs[s][a][0].data_ptr() for s in range(ns) for a in range(na)])
     dp = (P * max(ns * na, 1))(*[outs[s][a][1].data_ptr() for s in range(ns) for a in range(na)])
-    opt = options(mode, False, tile, False)
+    opt = options(mode, False, tile, False, None)
     rc = lib().seg_segment_batch(ah, na, fp, nf, ns, lp, dp, ctypes.byref(opt), _stream(stream))
     _check(rc)
     return outs

@@ -20,7 +20,8 @@ from gpu_common import assert_parity, run, to_gpu
 
 pytestmark = pytest.mark.gpu
 
-FILTERED_MODES = ["plain"]
+PREFILTER_MODES = ["bf16", "fp16", "fp8", "bf16_oriented"]
+FILTERED_MODES = ["plain"] + PREFILTER_MODES
 ALL_MODES = ["dense"] + FILTERED_MODES
 
 
@@ -69,7 +70,10 @@ def test_synthetic_ragged(seg, mode, n, nb, per, seed):
     assert (lab >= 0).mean() > 0.3
 
 
-@pytest.mark.parametrize("mode,tiles", [("dense", [1, 2]), ("plain", [1, 2, 4])])
+@pytest.mark.parametrize("mode,tiles", [("dense", [1, 2]), ("plain", [1, 2, 4]),
+                                        ("bf16", [1, 2, 3, 4, 5, 6, 7]),
+                                        ("fp16", [1, 2, 4, 6]), ("fp8", [1, 2, 4, 6]),
+                                        ("bf16_oriented", [1, 2])])
 def test_tiles_identical(seg, mode, tiles):
     fib, at = synth.small_case(5000, 10, 31, seed=9)
     outs = []
@@ -177,15 +181,28 @@ def test_validation_errors(seg):
         seg.segment(f.cpu(), c, b, t)
 
 
-def test_filter_keeps_accepted_pairs_plain(seg):
-    fib, at = synth.small_case(2000, 6, 20, seed=15)
-    acc = oracle.accepted_pairs_f32(fib, at.centroids, at.bundle_id, at.thresholds)
-    f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
-    pairs = seg.filter_pairs(f, c, b, t, mode="plain").cpu().numpy().astype(np.int64)
+@pytest.mark.parametrize("mode", FILTERED_MODES)
+@pytest.mark.parametrize("case", ["synthetic", "adversarial"])
+def test_filter_keeps_accepted_pairs(seg, mode, case):
+    """Zero false discards: every pair the oracle accepts survives the first cut."""
+    if case == "synthetic":
+        fib, at = synth.small_case(2000, 6, 20, seed=15)
+        cen, bid, thr = at.centroids, at.bundle_id, at.thresholds
+    else:
+        fib, cen, bid, thr = _adversarial()
+    acc = oracle.accepted_pairs_f32(fib, cen, bid, thr)
+    f, c, b, t = to_gpu(fib, cen, bid, thr)
+    log(f"filter pairs mode={mode} case={case}")
+    pairs = seg.filter_pairs(f, c, b, t, mode=mode, capacity=1 << 22)
+    pairs = pairs.cpu().numpy().astype(np.int64)
     surv = set(map(tuple, pairs.tolist()))
     missing = [p for p in map(tuple, acc.tolist()) if p not in surv]
-    assert not missing, f"center test dropped {len(missing)} accepted pairs"
-    assert len(acc) > 500
+    assert not missing, f"{mode} dropped {len(missing)} accepted pairs, e.g. {missing[:3]}"
+    assert len(acc) > (1000 if case == "synthetic" else 250)
+    frac = len(pairs) / (len(fib) * len(cen))
+    log(f"  survivors {len(pairs)} ({frac:.2e} of pairs), accepted {len(acc)}")
+    if mode != "fp8":
+        assert frac < 0.05, f"{mode} cut keeps {frac:.2%} of pairs"
 
 
 def test_stats_and_determinism(seg):

@@ -21,10 +21,11 @@ def test_default_options():
     o = S.Options()
     P.lib().seg_default_options(ctypes.byref(o))
     assert (o.mode, o.validate, o.tile, o.collect_stats) == (S.PLAIN, 0, 0, 0)
+    assert o.profile_events is None
 
 
 def _call(n=10, m=5, nb=2, mode=S.PLAIN, fib=8, cen=16, bid=32, thr=48, lab=64, dist=80):
-    o = S.Options(mode, 0, 0, 0)
+    o = S.Options(mode, 0, 0, 0, None)
     return P.lib().seg_segment(fib, n, cen, m, bid, thr, nb, lab, dist, ctypes.byref(o), None)
 
 
@@ -54,7 +55,7 @@ def test_filter_and_batch_host_errors():
     cnt = ctypes.c_int64(7)
     assert L.seg_filter_pairs(8, 4, 16, 3, 32, 48, 1, 99, 64, 10, ctypes.byref(cnt), None) == -7
     assert L.seg_filter_pairs(8, -4, 16, 3, 32, 48, 1, 1, 64, 10, ctypes.byref(cnt), None) == -1
-    o = S.Options(S.PLAIN, 0, 0, 0)
+    o = S.Options(S.PLAIN, 0, 0, 0, None)
     assert L.seg_segment_batch(None, 1, None, None, 1, None, None, ctypes.byref(o), None) == -1
     h = ctypes.c_void_p()
     assert L.seg_atlas_create(16, -2, 32, 48, 1, None, ctypes.byref(h)) == -1
