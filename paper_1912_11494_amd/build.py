@@ -26,6 +26,9 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA operands and results in ordinary VGPRs, so the VALU epilogue reads
+    # them directly (no copies out of accumulation registers)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",

@@ -175,109 +175,190 @@ __device__ void features(const float* __restrict__ p, const double* o, bool rev,
 }
 
 // Origin, fp8 scale: one block over the prepared centroid records.
+constexpr int EMAX_SLOTS = 64;
+
 struct PfParams {
-  float o[3];
-  float scale;  // features are stored multiplied by `scale` (a power of two)
-  float scale2;
-  unsigned int emax_bits;  // largest fiber quantisation error (float bits)
+  // bounding box of the atlas points as order-preserving integers
+  int lo[3], hi[3];
+  // largest fiber quantisation error (float bits), spread over slots so that
+  // the per-wave atomics do not all hit one address; the maximum is the
+  // maximum over the slots
+  unsigned int emax_bits[EMAX_SLOTS];
 };
 
-__global__ __launch_bounds__(1024) void pf_params_kernel(const float* __restrict__ cprep, int32_t m,
-                                                         int q, PfParams* __restrict__ prm) {
-  __shared__ float smin[3][1024], smax[3][1024];
-  float lo[3] = {3.4e38f, 3.4e38f, 3.4e38f}, hi[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
-  for (int64_t i = threadIdx.x; i < (int64_t)m * NP; i += blockDim.x) {
-    const float* p = cprep + (i / NP) * CREC + 3 * (i % NP);
+// float <-> int with the same order (for atomic min / max of floats)
+__device__ __forceinline__ int ord(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float unord(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
+
+// Origin (the middle of the atlas box, rounded to a whole millimetre) and the
+// power-of-two scale of the stored codes (1 except for fp8, where the largest
+// feature, about sqrt(3) times the half extent, must stay under 448).
+struct Frame {
+  double o[3];
+  double s, is, s2;
+};
+
+__device__ __forceinline__ Frame frame(const PfParams* __restrict__ prm, int q) {
+  Frame fr;
+  float ext = 0.0f;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fminf(lo[d], p[d]);
-      hi[d] = fmaxf(hi[d], p[d]);
+  for (int d = 0; d < 3; ++d) {
+    const float lo = unord(prm->lo[d]), hi = unord(prm->hi[d]);
+    const float c = rintf(0.5f * lo + 0.5f * hi);
+    fr.o[d] = c;
+    ext = fmaxf(ext, fmaxf(hi - c, c - lo));
+  }
+  float sc = 1.0f;
+  if (q == Q_FP8) sc = exp2f(floorf(log2f(448.0f / fmaxf(2.0f * ext, 1e-3f))));
+  fr.s = sc;
+  fr.is = 1.0 / (double)sc;  // exact: a power of two
+  fr.s2 = (double)sc * sc;
+  return fr;
+}
+
+__global__ void pf_init_kernel(PfParams* __restrict__ prm) {
+  const int t = threadIdx.x;
+  if (t < 3) {
+    prm->lo[t] = ord(__builtin_inff());
+    prm->hi[t] = ord(-__builtin_inff());
+  }
+  if (t < EMAX_SLOTS) prm->emax_bits[t] = 0u;
+}
+
+// One thread per centroid; wave-reduced, then one atomic per wave and axis.
+__global__ __launch_bounds__(256) void pf_bbox_kernel(const float* __restrict__ cprep, int32_t m,
+                                                      PfParams* __restrict__ prm) {
+  const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  if (c < m) {
+    const float* p = cprep + (int64_t)c * CREC;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float v = p[3 * i + d];
+        if (__builtin_isfinite(v)) {
+          lo[d] = fminf(lo[d], v);
+          hi[d] = fmaxf(hi[d], v);
+        }
+      }
     }
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    smin[d][threadIdx.x] = lo[d];
-    smax[d][threadIdx.x] = hi[d];
-  }
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        smin[d][threadIdx.x] = fminf(smin[d][threadIdx.x], smin[d][threadIdx.x + w]);
-        smax[d][threadIdx.x] = fmaxf(smax[d][threadIdx.x], smax[d][threadIdx.x + w]);
-      }
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = fminf(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    float ext = 0.0f;
+  if (lane_id() == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      // origin: the middle of the atlas box, rounded to a whole millimetre
-      const float c = rintf(0.5f * (smin[d][0] + smax[d][0]));
-      prm->o[d] = c;
-      ext = fmaxf(ext, fmaxf(smax[d][0] - c, c - smin[d][0]));
+      atomicMin(&prm->lo[d], ord(lo[d]));
+      atomicMax(&prm->hi[d], ord(hi[d]));
     }
-    float s = 1.0f;
-    if (q == Q_FP8) {
-      // the largest feature is about sqrt(3) * ext; keep it under 448 with room
-      s = exp2f(floorf(log2f(448.0f / fmaxf(2.0f * ext, 1e-3f))));
-    }
-    prm->scale = s;
-    prm->scale2 = s * s;
-    prm->emax_bits = 0u;
   }
 }
 
 __device__ __forceinline__ double gamma_acc(int kp) { return 4.0 * (kp + 2) * 0x1p-24; }
 
-// One thread per fiber: quantised features (row-major [n_pad][KP]), the row
-// constant -Ha (MFMA C operand) and the device maximum of the error.
+// Quantise the features of one curve: packs the KP codes into `row` (16-byte
+// stores), returns |Xq|^2 in *nq and the error bound |Xq - X| in *e; both are
+// non-finite when a coordinate is.
 template <int Q, int MAPK, int KP>
-__global__ __launch_bounds__(256) void pf_fiber_kernel(const float* __restrict__ fibers, int64_t n,
-                                                       int64_t n_pad, PfParams* __restrict__ prm,
-                                                       uint8_t* __restrict__ feat,
-                                                       float* __restrict__ negh) {
+__device__ __forceinline__ void quantise_row(const float* __restrict__ p, bool rev,
+                                             const PfParams* __restrict__ prm,
+                                             uint8_t* __restrict__ row, double* nq_out,
+                                             double* e_out) {
   using T = QTraits<Q>;
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_pad) return;
-  uint8_t* row = feat + f * (KP * T::bytes);
-  if (f >= n) {  // padding rows: zero features, never pass
-    for (int k = 0; k < KP * T::bytes; ++k) row[k] = 0;
-    negh[f] = -__builtin_inff();
-    return;
-  }
-  const double o[3] = {prm->o[0], prm->o[1], prm->o[2]};
-  const double s = prm->scale;
+  const Frame fr = frame(prm, Q);
+  const double s = fr.s, is = fr.is;
   double x[KP];
-  features<MAPK, KP>(fibers + f * NF, o, false, x);
+  features<MAPK, KP>(p, fr.o, rev, x);
   double nq = 0.0, err = 0.0, nx = 0.0;
+  constexpr int PER = 16 / T::bytes;  // codes per 16-byte store
+  uint32_t w[4];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const uint32_t b = T::enc(x[k] * s);
-    const double xq = T::dec(b) / s;  // exact (power-of-two scale)
-    if constexpr (T::bytes == 2) {
-      ((uint16_t*)row)[k] = (uint16_t)b;
-    } else {
-      row[k] = (uint8_t)b;
-    }
+    const double xq = T::dec(b) * is;  // exact (power-of-two scale)
+    const int j = k % PER;
+    const int word = j * T::bytes / 4, sh = (j * T::bytes % 4) * 8;
+    w[word] = (sh == 0 ? 0u : w[word]) | (b << sh);
+    if (j == PER - 1) *(uint4*)(row + (k / PER) * 16) = make_uint4(w[0], w[1], w[2], w[3]);
     nq += xq * xq;
     err += (xq - x[k]) * (xq - x[k]);
     nx += x[k] * x[k];
   }
-  if (!__builtin_isfinite(err + nx + nq)) {
+  *nq_out = nq;
+  // the double features themselves (square roots) carry 2^-50 relative error
+  *e_out = sqrt(err) * (1.0 + 0x1p-40) + 0x1p-50 * sqrt(nx) + 1e-30;
+  if (!__builtin_isfinite(err + nx + nq)) *e_out = __builtin_nan("");
+}
+
+template <int Q, int MAPK, int KP>
+__device__ __forceinline__ void fiber_feature_row(const float* __restrict__ p, int64_t f,
+                                                  int64_t n, const PfParams* __restrict__ prm,
+                                                  uint8_t* __restrict__ row,
+                                                  float* __restrict__ negh, float* e_out) {
+  if (f >= n) {  // padding rows: zero features, never pass
+#pragma unroll
+    for (int k = 0; k < KP * QTraits<Q>::bytes; k += 16) *(uint4*)(row + k) = make_uint4(0, 0, 0, 0);
+    negh[f] = -__builtin_inff();
+    return;
+  }
+  double nq, e;
+  quantise_row<Q, MAPK, KP>(p, false, prm, row, &nq, &e);
+  if (!__builtin_isfinite(e)) {
     // a non-finite coordinate: bypass the cut (always survive) and leave the
     // error bound of the other fibers alone; the exact stage decides
     negh[f] = __builtin_inff();
     return;
   }
-  // error of the double features themselves (square roots): 2^-50 relative
-  const double e = sqrt(err) * (1.0 + 0x1p-40) + 0x1p-50 * sqrt(nx) + 1e-30;
   const double g = gamma_acc(KP);
   const double ha = (0.5 - g) * nq * (1.0 - 0x1p-40);  // round towards passing
-  negh[f] = __double2float_ru(-ha * prm->scale2);
-  atomicMax(&prm->emax_bits, __float_as_uint(__double2float_ru(e)));
+  negh[f] = __double2float_ru(-ha * frame(prm, Q).s2);
+  *e_out = __double2float_ru(e);
+}
+
+// One wave per 64 fibers: the wave copies its 64 records (16 KB, contiguous)
+// into LDS with coalesced loads, then each lane computes the quantised
+// features of its fiber (row-major [n_pad][KP]), the row constant -Ha (MFMA
+// C operand) and the wave's largest error, folded into the device maximum
+// with one atomic.
+template <int Q, int MAPK, int KP>
+__global__ __launch_bounds__(64) void pf_fiber_kernel(const float* __restrict__ fibers, int64_t n,
+                                                      int64_t n_pad, PfParams* __restrict__ prm,
+                                                      uint8_t* __restrict__ feat,
+                                                      float* __restrict__ negh) {
+  using T = QTraits<Q>;
+  __shared__ float s_rec[64 * NF];
+  const int lane = (int)threadIdx.x;
+  const int64_t f0 = (int64_t)blockIdx.x * 64;
+  const int64_t nrec = n - f0 < 64 ? (n - f0 > 0 ? n - f0 : 0) : 64;
+  const float* src = fibers + f0 * NF;
+  if (nrec == 64) {
+    // all 63 coalesced loads in flight at once, then the LDS writes
+    float v[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) v[j] = src[j * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) s_rec[j * 64 + lane] = v[j];
+  } else {
+    for (int64_t i = lane; i < nrec * NF; i += 64) s_rec[i] = src[i];
+  }
+  __syncthreads();
+  const int64_t f = f0 + lane;
+  float e32 = 0.0f;  // every lane reaches the wave maximum below
+  if (f < n_pad)
+    fiber_feature_row<Q, MAPK, KP>(s_rec + lane * NF, f, n, prm, feat + f * (KP * T::bytes), negh,
+                                   &e32);
+  for (int off = 32; off > 0; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off));
+  if (lane == 0) atomicMax(&prm->emax_bits[blockIdx.x % EMAX_SLOTS], __float_as_uint(e32));
 }
 
 // One thread per column (centroid, or centroid x order): features and cb.
@@ -294,47 +375,34 @@ __global__ __launch_bounds__(256) void pf_column_kernel(const float* __restrict_
   uint8_t* row = feat + (int64_t)col * (KP * T::bytes);
   const int32_t c = col / MI::CPC;
   if (c >= m) {  // padding columns never pass
-    for (int k = 0; k < KP * T::bytes; ++k) row[k] = 0;
+#pragma unroll
+    for (int k = 0; k < KP * T::bytes; k += 16) *(uint4*)(row + k) = make_uint4(0, 0, 0, 0);
     cb[col] = __builtin_inff();
     return;
   }
   const float* p = cprep + (int64_t)c * CREC;
   const float t2 = p[NF];
-  const double o[3] = {prm->o[0], prm->o[1], prm->o[2]};
-  const double s = prm->scale;
-  double x[KP];
-  features<MAPK, KP>(p, o, (col % MI::CPC) == 1, x);
-  double nq = 0.0, err = 0.0, nx = 0.0;
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const uint32_t b = T::enc(x[k] * s);
-    const double xq = T::dec(b) / s;
-    if constexpr (T::bytes == 2) {
-      ((uint16_t*)row)[k] = (uint16_t)b;
-    } else {
-      row[k] = (uint8_t)b;
-    }
-    nq += xq * xq;
-    err += (xq - x[k]) * (xq - x[k]);
-    nx += x[k] * x[k];
-  }
+  double nq, eb;
+  quantise_row<Q, MAPK, KP>(p, (col % MI::CPC) == 1, prm, row, &nq, &eb);
   if (!(t2 >= 0.0f)) {  // bundle never matches
     cb[col] = __builtin_inff();
     return;
   }
-  if (__builtin_isinf(t2) || !__builtin_isfinite(err + nx + nq)) {
+  if (__builtin_isinf(t2) || !__builtin_isfinite(eb)) {
     // bundle always matches, or a non-finite coordinate: always survive
     cb[col] = -__builtin_inff();
     return;
   }
-  const double eb = sqrt(err) * (1.0 + 0x1p-40) + 0x1p-50 * sqrt(nx) + 1e-30;
-  const double E = (double)__uint_as_float(prm->emax_bits);
+  unsigned int eb_bits = 0u;
+#pragma unroll 8
+  for (int i = 0; i < EMAX_SLOTS; ++i) eb_bits = max(eb_bits, prm->emax_bits[i]);
+  const double E = (double)__uint_as_float(eb_bits);
   const double R = sqrt((double)MI::G * (double)t2 / (1.0 - 8.0 * 0x1p-24)) * (1.0 + 0x1p-40);
   const double S = (R + E + eb) * (1.0 + 0x1p-40);
   const double g = gamma_acc(KP);
   double v = 0.5 * (nq - S * S) - 0.5 * g * nq;
   v -= fabs(v) * 0x1p-40;  // round towards passing
-  cb[col] = __double2float_rd(v * prm->scale2);
+  cb[col] = __double2float_rd(v * frame(prm, Q).s2);
 }
 
 // ------------------------------------------------------------------ fused kernel
@@ -359,17 +427,44 @@ template <> struct Frag<Q_FP8> {
   }
 };
 
+// Largest of a lane's 16 outputs as a tree of three-input maxima (depth 3,
+// so the reduction does not serialise on one dependency chain).
+__device__ __forceinline__ float max16(const f32x16& a) {
+  const float m0 = __builtin_fmaxf(__builtin_fmaxf(a[0], a[1]), a[2]);
+  const float m1 = __builtin_fmaxf(__builtin_fmaxf(a[3], a[4]), a[5]);
+  const float m2 = __builtin_fmaxf(__builtin_fmaxf(a[6], a[7]), a[8]);
+  const float m3 = __builtin_fmaxf(__builtin_fmaxf(a[9], a[10]), a[11]);
+  const float m4 = __builtin_fmaxf(__builtin_fmaxf(a[12], a[13]), a[14]);
+  const float n0 = __builtin_fmaxf(__builtin_fmaxf(m0, m1), m2);
+  const float n1 = __builtin_fmaxf(__builtin_fmaxf(m3, m4), a[15]);
+  return __builtin_fmaxf(n0, n1);
+}
+
 // Row of lane l's output register r in a 32x32 MFMA tile.
 __device__ __forceinline__ int out_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
 
+// Centroid tiles per LDS chunk for a feature width.
+template <int KP> struct Chunk { static constexpr int CH = KP <= 32 ? 8 : (KP <= 48 ? 4 : 2); };
+
 // Rows = fibers (A operand, held in registers for the whole kernel), columns
-// = centroid columns (B operand, streamed 32 at a time).  Each wave owns GF
-// groups of 32 fibers.  Per 32-column tile and group: KP/16 MFMAs starting
-// from C = -Ha, then the largest of the lane's 16 outputs is compared with
-// the column constant cb.  A lane above it has a survivor among its rows; the
-// wave then pushes every (fiber, centroid) above cb into its LDS queue (ballot
-// + prefix count), drained by the exact stage as in the plain pass.  With
-// PAIRS, survivors are written to a global list instead (diagnostics).
+// = centroid columns (B operand).  Each wave owns GF groups of 32 fibers; the
+// four waves of a block share the centroid stream.
+//
+// Centroid stream: chunks of CH tiles (32 columns each) pass through three
+// LDS buffers.  During chunk k every thread holds chunk k+2 in registers
+// (loaded from global at the start of the chunk) and writes it to the buffer
+// of chunk k-1 at the end; one barrier per chunk then makes it visible.  The
+// MFMAs of tile t+1 are issued before the epilogue of tile t (two
+// accumulator sets), also across chunk boundaries, so the matrix unit works
+// while the VALU reduces.
+//
+// Per tile and group: KP/16 MFMAs starting from C = -Ha, then the largest of
+// the lane's 16 outputs is compared with the column constant cb; the hot loop
+// only records which (tile, group) has a lane above it.  After the loop those
+// few are recomputed and every (fiber, centroid) above cb is pushed into the
+// wave's LDS queue (ballot + prefix count), drained by the exact stage as in
+// the plain pass.  With PAIRS, survivors are written to a global list instead
+// (diagnostics).
 template <int Q, int KP, int GF, int CPC, bool STATS, bool PAIRS>
 __global__ __launch_bounds__(256) void prefilter_kernel(
     const uint8_t* __restrict__ ffeat, const float* __restrict__ fnegh,
@@ -382,14 +477,24 @@ __global__ __launch_bounds__(256) void prefilter_kernel(
   constexpr int EB = QTraits<Q>::bytes;
   constexpr int WAVES = 4;
   constexpr int FPW = GF * 32;
+  constexpr int CH = Chunk<KP>::CH;
+  constexpr int CCOLS = 32 * CH;  // columns per chunk (<= 256 = one per thread)
   // A group of 32 fibers x 32 columns adds at most 1024 entries; the queue is
   // drained before a group whenever that might not fit.
   constexpr int QCAP = 2048;
   static_assert(FPW <= 256, "slot must fit 8 bits");
+  static_assert(CCOLS <= 256, "one chunk column per thread");
+  static_assert(CH % 2 == 0, "accumulator sets alternate within a chunk");
+  __shared__ FT s_feat[3][CH][KS][2][32];
+  __shared__ float s_cb[3][CH][32];
+  // (tile, group) pairs with a survivor, processed after the centroid loop
+  constexpr int HCAP = 512;
+  __shared__ uint32_t s_hits[WAVES][HCAP];
   __shared__ uint32_t s_queue[PAIRS ? 1 : WAVES][PAIRS ? 1 : QCAP];
   __shared__ uint64_t s_keys[PAIRS ? 1 : WAVES][PAIRS ? 1 : FPW];
-  const int lane = (int)(threadIdx.x & 63u);
-  const int wave = (int)(threadIdx.x >> 6);
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int half = lane >> 5;
   const int64_t wbase = ((int64_t)blockIdx.x * WAVES + wave) * FPW;
   WaveQueue wq{PAIRS ? nullptr : s_queue[wave], PAIRS ? nullptr : s_keys[wave]};
@@ -416,59 +521,152 @@ __global__ __launch_bounds__(256) void prefilter_kernel(
     for (int k = lane; k < FPW; k += 64) wq.keys[k] = NO_KEY;
   }
   const float* fib_base = fibers + (wbase < n ? wbase : 0) * NF;
+  const int32_t nchunks = ncols_pad / CCOLS;
 
+  // chunk staging: thread tid < CCOLS owns chunk column tid
+  FT gfe[KS][2];
+  float gcb = 0.0f;
+  auto gload = [&](int32_t chunk) {
+    if (tid < CCOLS && chunk < nchunks) {
+      const int64_t col = (int64_t)chunk * CCOLS + tid;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          gfe[s][h] = *(const FT*)(cfeat + col * (KP * EB) + (s * 16 + 8 * h) * EB);
+      gcb = cbias[col];
+    }
+  };
+  auto lstore = [&](int buf, int32_t chunk) {
+    if (tid < CCOLS && chunk < nchunks) {
+      const int tl = tid >> 5, j = tid & 31;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) s_feat[buf][tl][s][h][j] = gfe[s][h];
+      s_cb[buf][tl][j] = gcb;
+    }
+  };
+  gload(0);
+  lstore(0, 0);
+  gload(1);
+  lstore(1, 1);
+  __syncthreads();
+
+  // Three stages per tile: the fragment of tile t+2 is read from LDS, the
+  // MFMAs of tile t+1 are issued (its fragment was read one step earlier),
+  // and the epilogue of tile t runs on the products issued one step earlier.
+  FT frag[2][KS];
+  float fcb[2];
+  auto fetch = [&](int set, int bufx, int tl) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) frag[set][s] = s_feat[bufx][tl][s][half][lane & 31];
+    fcb[set] = s_cb[bufx][tl][lane & 31];
+  };
+  f32x16 acc[2][GF];
+  float cbc[2];
+  auto issue = [&](int set, int fset) {
+#pragma unroll
+    for (int g = 0; g < GF; ++g) {
+      acc[set][g] = Frag<Q>::mfma(afr[g][0], frag[fset][0], negh[g]);
+#pragma unroll
+      for (int s = 1; s < KS; ++s) acc[set][g] = Frag<Q>::mfma(afr[g][s], frag[fset][s], acc[set][g]);
+    }
+    cbc[set] = fcb[fset];
+  };
+  // tile 0 issued, tile 1 fetched (both in chunk 0 since CH >= 2)
+  fetch(0, 0, 0);
+  issue(0, 0);
+  fetch(1, 0, 1);
+
+  // Survivor extraction for one (tile, group): the products are recomputed
+  // (one more MFMA; hits are rare) and every (fiber, centroid) above cb is
+  // pushed.  `b` and `cb` are the tile's fragment and column constant.
   uint32_t qn = 0;
-  const int32_t ntiles = ncols_pad / 32;
-  for (int32_t t = 0; t < ntiles; ++t) {
-    const int32_t col = t * 32 + (lane & 31);
-    FT bfr[KS];
+  auto extract = [&](const FT* b, float cb, int32_t tile, int g) {
+    f32x16 a = Frag<Q>::mfma(afr[g][0], b[0], negh[g]);
+#pragma unroll
+    for (int s = 1; s < KS; ++s) a = Frag<Q>::mfma(afr[g][s], b[s], a);
+    const int32_t col = tile * 32 + (lane & 31);
+    const uint32_t cent = (uint32_t)(col / CPC);
+    if (!PAIRS && qn > (uint32_t)(QCAP - 1024)) {
+      queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
+      qn = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int slot = g * 32 + out_row(lane, r);
+      const bool p = a[r] >= cb && wbase + slot < n;
+      const uint64_t msk = __ballot(p);
+      if (!msk) continue;
+      if (PAIRS) {
+        if (p) {
+          const unsigned long long kk = atomicAdd(counters, 1ull);
+          if ((int64_t)kk < cap) {
+            pairs[2 * kk] = (int32_t)(wbase + slot);
+            pairs[2 * kk + 1] = (int32_t)cent;
+          }
+        }
+      } else {
+        queue_push(wq, qn, msk, (cent << 8) | (uint32_t)slot);
+      }
+    }
+  };
+  auto extract_global = [&](int32_t tile, int g) {
+    const int32_t col = tile * 32 + (lane & 31);
+    FT b[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
-      bfr[s] = *(const FT*)(cfeat + (int64_t)col * (KP * EB) + (s * 16 + 8 * half) * EB);
+      b[s] = *(const FT*)(cfeat + (int64_t)col * (KP * EB) + (s * 16 + 8 * half) * EB);
     const float cb = cbias[col];
-    f32x16 acc[GF];
-    bool hit[GF];
-    bool anyhit = false;
 #pragma unroll
-    for (int g = 0; g < GF; ++g) {
-      acc[g] = Frag<Q>::mfma(afr[g][0], bfr[0], negh[g]);
+    for (int gg = 0; gg < GF; ++gg)
+      if (gg == g) extract(b, cb, tile, gg);
+  };
+
+  // The hot loop only records hits (wave-uniform list in LDS); extraction
+  // happens after the loop so that the waves of a block stay in step between
+  // barriers.  A full list falls back to extracting at once.
+  uint32_t nh = 0;
+  uint32_t* hl = s_hits[wave];
+  int buf = 0;
+  for (int32_t k = 0; k < nchunks; ++k) {
+    gload(k + 2);
+    const int nbuf = buf == 2 ? 0 : buf + 1;
+    const int fbuf = k + 1 < nchunks ? nbuf : buf;  // past the end: harmless re-reads
 #pragma unroll
-      for (int s = 1; s < KS; ++s) acc[g] = Frag<Q>::mfma(afr[g][s], bfr[s], acc[g]);
-      float mx = fmaxf(fmaxf(acc[g][0], acc[g][1]), acc[g][2]);
+    for (int u = 0; u < CH; ++u) {
+      // tile u+1 was fetched into set (u+1)&1 one step ago: issue it; then
+      // fetch tile u+2 into the set just consumed (u&1)
+      issue((u + 1) & 1, (u + 1) & 1);
+      if (u + 2 < CH)
+        fetch(u & 1, buf, u + 2);
+      else
+        fetch(u & 1, fbuf, u + 2 - CH);
+      const int cs = u & 1;
+      const float cb = cbc[cs];
 #pragma unroll
-      for (int r = 3; r < 15; r += 2) mx = fmaxf(fmaxf(mx, acc[g][r]), acc[g][r + 1]);
-      mx = fmaxf(mx, acc[g][15]);
-      hit[g] = mx >= cb;
-      anyhit = anyhit || hit[g];
-    }
-    if (!wave_any(anyhit)) continue;
-    const uint32_t cent = (uint32_t)(col / CPC);
-#pragma unroll
-    for (int g = 0; g < GF; ++g) {
-      if (!wave_any(hit[g])) continue;
-      if (!PAIRS && qn > (uint32_t)(QCAP - 1024)) {
-        queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
-        qn = 0;
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int slot = g * 32 + out_row(lane, r);
-        const bool p = hit[g] && acc[g][r] >= cb && wbase + slot < n;
-        const uint64_t msk = __ballot(p);
-        if (!msk) continue;
-        if (PAIRS) {
-          if (p) {
-            const unsigned long long k = atomicAdd(counters, 1ull);
-            if ((int64_t)k < cap) {
-              pairs[2 * k] = (int32_t)(wbase + slot);
-              pairs[2 * k + 1] = (int32_t)cent;
-            }
+      for (int g = 0; g < GF; ++g) {
+        const float mx = max16(acc[cs][g]);
+        if (wave_any(mx >= cb)) {
+          const int32_t tile = k * CH + u;
+          if (nh < (uint32_t)HCAP) {
+            if (lane == 0) hl[nh] = ((uint32_t)tile << 3) | (uint32_t)g;
+            ++nh;
+          } else {
+            extract_global(tile, g);
           }
-        } else {
-          queue_push(wq, qn, msk, (cent << 8) | (uint32_t)slot);
         }
       }
     }
+    // chunk k+2 goes into the buffer of chunk k-1 (nobody reads it any more)
+    lstore(buf == 0 ? 2 : buf - 1, k + 2);
+    __syncthreads();
+    buf = nbuf;
+  }
+  for (uint32_t i = 0; i < nh; ++i) {
+    const uint32_t e = hl[i];
+    extract_global((int32_t)(e >> 3), (int)(e & 7u));
   }
   if (PAIRS) return;
   queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
@@ -519,7 +717,7 @@ int resolve(int mode, int tile, Cfg* c) {
     case 0:
     case 1: c->kp = 16; c->gf = 2; break;
     case 2: c->kp = 16; c->gf = 4; break;
-    case 3: c->kp = 16; c->gf = 8; break;
+    case 3: c->kp = 16; c->gf = 1; break;
     case 4: c->kp = 32; c->gf = 2; break;
     case 5: c->kp = 32; c->gf = 4; break;
     case 6: c->kp = 48; c->gf = 2; break;
@@ -538,7 +736,8 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
   constexpr int FPB = 4 * GF * 32;  // fibers per block
   const int64_t n_pad = (n + FPB - 1) / FPB * FPB;
   const int32_t ncols = m * MI::CPC;
-  const int32_t ncols_pad = (ncols + 31) / 32 * 32;
+  constexpr int CC = 32 * Chunk<KP>::CH;  // columns per LDS chunk
+  const int32_t ncols_pad = (ncols + CC - 1) / CC * CC;
   int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)n_pad * KP * EB);
   rc = rc ? rc : grow((void**)&pb.fib_h, &pb.fib_h_bytes, (size_t)n_pad * sizeof(float));
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
@@ -548,8 +747,9 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
   PfParams* prm = (PfParams*)pb.emax;
   uint8_t* cfeat = (uint8_t*)pb.cen_feat;
   float* cb = (float*)(cfeat + (size_t)ncols_pad * KP * EB);
-  pf_params_kernel<<<1, 1024, 0, s>>>(cprep, m, Q, prm);
-  pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)((n_pad + 255) / 256), 256, 0, s>>>(
+  pf_init_kernel<<<1, 64, 0, s>>>(prm);
+  pf_bbox_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, prm);
+  pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)((n_pad + 63) / 64), 64, 0, s>>>(
       fibers, n, n_pad, prm, (uint8_t*)pb.fib_feat, pb.fib_h);
   pf_column_kernel<Q, MAPK, KP><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
       cprep, m, ncols_pad, prm, cfeat, cb);
@@ -582,21 +782,21 @@ int dispatch(const Cfg& c, const float* fibers, int64_t n, const float* cprep, i
                                       cap, pb, ev, s);
   SEG_PF(Q_BF16, MAP_SYM, 16, 2)
   SEG_PF(Q_BF16, MAP_SYM, 16, 4)
-  SEG_PF(Q_BF16, MAP_SYM, 16, 8)
+  SEG_PF(Q_BF16, MAP_SYM, 16, 1)
   SEG_PF(Q_BF16, MAP_SYM, 32, 2)
   SEG_PF(Q_BF16, MAP_SYM, 32, 4)
   SEG_PF(Q_BF16, MAP_SYM, 48, 2)
   SEG_PF(Q_BF16, MAP_SYM, 48, 4)
   SEG_PF(Q_F16, MAP_SYM, 16, 2)
   SEG_PF(Q_F16, MAP_SYM, 16, 4)
-  SEG_PF(Q_F16, MAP_SYM, 16, 8)
+  SEG_PF(Q_F16, MAP_SYM, 16, 1)
   SEG_PF(Q_F16, MAP_SYM, 32, 2)
   SEG_PF(Q_F16, MAP_SYM, 32, 4)
   SEG_PF(Q_F16, MAP_SYM, 48, 2)
   SEG_PF(Q_F16, MAP_SYM, 48, 4)
   SEG_PF(Q_FP8, MAP_SYM, 16, 2)
   SEG_PF(Q_FP8, MAP_SYM, 16, 4)
-  SEG_PF(Q_FP8, MAP_SYM, 16, 8)
+  SEG_PF(Q_FP8, MAP_SYM, 16, 1)
   SEG_PF(Q_FP8, MAP_SYM, 32, 2)
   SEG_PF(Q_FP8, MAP_SYM, 32, 4)
   SEG_PF(Q_FP8, MAP_SYM, 48, 2)
