@@ -145,8 +145,12 @@ int seg_segment_atlas(const seg_atlas* atlas, const float* fibers, int64_t n_fib
                       int32_t* labels, float* dists, const seg_options* opt, void* stream);
 
 /*
- * Segment n_subjects subjects against n_atlases prepared atlases in one
- * persistent launch (replayed from a cached HIP graph when the shapes repeat).
+ * Segment n_subjects subjects against n_atlases prepared atlases with one
+ * launch of the fused kernel over a flattened list of (subject, atlas, fiber
+ * block) work items, costliest atlas first; the whole sequence (preparation
+ * kernels + that launch) is captured once per launch shape into a HIP graph
+ * and replayed on `stream`.  All subjects share one quantisation frame, so
+ * each subject's prefilter features are computed once for all atlases.
  *   atlases   host array [n_atlases] of handles
  *   fibers    host array [n_subjects] of device pointers ([n][21][3] float32)
  *   n_fibers  host array [n_subjects]
@@ -158,6 +162,26 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases,
                       const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
                       int32_t* const* labels, float* const* dists, const seg_options* opt,
                       void* stream);
+
+/* ---- autotuning ---- */
+
+/*
+ * Time every kernel configuration ("tile") of `mode` on these inputs (device
+ * fibers [n][21][3] against a prepared atlas, `reps` timed calls each after
+ * one warm-up, HIP events on `stream`) and remember the fastest for calls
+ * with tile = 0 whose mode and sizes fall in the same bucket (mode,
+ * floor(log2 N), floor(log2 M)).  Writes the winner and its mean time (ms)
+ * when the pointers are not NULL.  Allocates and frees temporary outputs;
+ * synchronises `stream`.  Batches use the bucket of their largest subject.
+ */
+int seg_autotune(const seg_atlas* atlas, const float* fibers, int64_t n_fibers, int32_t mode,
+                 int32_t reps, int32_t* best_tile, float* best_ms, void* stream);
+
+/* Save / load the tuned choices as text lines "mode log2n log2m tile ms". */
+int seg_tune_save(const char* path);
+int seg_tune_load(const char* path);
+/* Forget every tuned choice. */
+void seg_tune_clear(void);
 
 /* ---- diagnostics ---- */
 

@@ -5,6 +5,10 @@ behind the C ABI of ``include/seg.h``); ``seg`` is its Python binding.
 """
 from .seg import (  # noqa: F401
     Atlas,
+    autotune,
+    tune_clear,
+    tune_load,
+    tune_save,
     DENSE,
     MODES,
     PLAIN,

@@ -2,10 +2,13 @@
 // The operation and its arithmetic contract are documented in include/seg.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <string>
 #include <utility>
+#include <tuple>
 #include <vector>
 
 #include "seg.h"
@@ -103,6 +106,39 @@ int get_scratch(hipStream_t s, Scratch** out) {
   return 0;
 }
 
+// Tuned tile per (mode, floor(log2 N), floor(log2 M)).
+struct Tuned {
+  int tile;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, Tuned> g_tuned;
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+int tuned_tile(int mode, int64_t n, int64_t m) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(mode, ilog2(n), ilog2(m)));
+  return it == g_tuned.end() ? 0 : it->second.tile;
+}
+
+// Kernel configurations of a mode (see the launchers).
+std::vector<int> mode_tiles(int mode) {
+  switch (mode) {
+    case SEG_DENSE: return {1, 2};
+    case SEG_PLAIN: return {1, 2, 4};
+    case SEG_PREFILTER_BF16_ORIENTED: return {1, 2};
+    default: return {1, 3, 4, 6};  // symmetric prefilters (K, fiber groups)
+  }
+}
+
 // State for seg_query_stats.
 thread_local unsigned long long* t_stats_counters = nullptr;
 thread_local hipStream_t t_stats_stream = nullptr;
@@ -178,26 +214,27 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
     return hip_fail(hipGetLastError(), "counter reset");
   const int32_t m = (int32_t)ab.m;
   hipEvent_t* ev = (hipEvent_t*)o.profile_events;
+  const int tile = o.tile ? o.tile : tuned_tile(o.mode, n, m);
   int rc = 0;
   switch (o.mode) {
     case SEG_DENSE:
       if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-      rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, o.tile, s);
+      rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, tile, s);
       if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     case SEG_PLAIN:
       if (ev) HIP_TRY(hipEventRecord(ev[0], s));
       rc = seg::launch_plain(fibers, n, ab.ccen, ab.cprep, m, ab.bid, labels, dists, counters,
-                             o.tile, s);
+                             tile, s);
       if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     default:
-      rc = seg::run_prefilter(o.mode, o.tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
+      rc = seg::run_prefilter(o.mode, tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
                               dists, counters, sc->pre, ev, s);
       if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
       break;
   }
-  if (rc == -2) return fail(SEG_EMODE, "unknown tile configuration " + std::to_string(o.tile));
+  if (rc == -2) return fail(SEG_EMODE, "unknown tile configuration " + std::to_string(tile));
   if (rc) return hip_fail(hipGetLastError(), "kernel launch");
   if (o.collect_stats) {
     t_stats_counters = counters;
@@ -384,12 +421,100 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
   for (int32_t a = 0; a < n_atlases; ++a)
     bav.push_back(seg::BatchAtlas{atlases[a]->buf.cprep, atlases[a]->buf.ccen,
                                   atlases[a]->buf.bid, (int32_t)atlases[a]->buf.m});
-  rc = seg::run_batch(o.mode, o.tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
+  int64_t nmax = 0, mmax = 0;
+  for (int32_t i = 0; i < n_subjects; ++i) nmax = n_fibers[i] > nmax ? n_fibers[i] : nmax;
+  for (const auto& a : bav) mmax = a.m > mmax ? a.m : mmax;
+  const int tile = o.tile ? o.tile : tuned_tile(o.mode, nmax, mmax);
+  rc = seg::run_batch(o.mode, tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
                       dists, sc->batch, sc->pre, s);
   if (rc == -2) return fail(SEG_EMODE, "mode not supported by the batch path");
   if (rc == -3) return fail(SEG_ENOMEM, "batch scratch allocation failed");
   if (rc) return hip_fail(hipGetLastError(), "batch launch");
   return SEG_OK;
+}
+
+int seg_autotune(const seg_atlas* a, const float* fibers, int64_t n, int32_t mode, int32_t reps,
+                 int32_t* best_tile, float* best_ms, void* stream) {
+  t_err.clear();
+  if (!a || !fibers || n <= 0) return fail(SEG_EINVAL, "autotune needs an atlas and fibers");
+  int rc = check_mode(mode);
+  if (rc) return rc;
+  if (reps <= 0) reps = 3;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* labels = nullptr;
+  float* dists = nullptr;
+  HIP_TRY(hipMalloc(&labels, (size_t)n * sizeof(int32_t)));
+  if (hipMalloc(&dists, (size_t)n * sizeof(float)) != hipSuccess) {
+    (void)hipFree(labels);
+    return fail(SEG_ENOMEM, "autotune output allocation failed");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = 0;
+  float best_t = 0.0f;
+  for (int tile : mode_tiles(mode)) {
+    seg_options o;
+    seg_default_options(&o);
+    o.mode = mode;
+    o.tile = tile;
+    rc = seg_segment_atlas(a, fibers, n, labels, dists, &o, stream);
+    if (rc) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !rc; ++r) rc = seg_segment_atlas(a, fibers, n, labels, dists, &o, stream);
+    (void)hipEventRecord(e1, s);
+    if (rc) break;
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (best == 0 || ms < best_t) {
+      best = tile;
+      best_t = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(labels);
+  (void)hipFree(dists);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple((int)mode, ilog2(n), ilog2(a->buf.m))] = Tuned{best, best_t};
+  }
+  if (best_tile) *best_tile = best;
+  if (best_ms) *best_ms = best_t;
+  return SEG_OK;
+}
+
+int seg_tune_save(const char* path) {
+  if (!path) return fail(SEG_EINVAL, "null path");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(SEG_EINVAL, std::string("cannot write ") + path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : g_tuned)
+    fprintf(f, "%d %d %d %d %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first),
+            std::get<2>(kv.first), kv.second.tile, kv.second.ms);
+  fclose(f);
+  return SEG_OK;
+}
+
+int seg_tune_load(const char* path) {
+  if (!path) return fail(SEG_EINVAL, "null path");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(SEG_EINVAL, std::string("cannot read ") + path);
+  int mode, ln, lm, tile;
+  float ms;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  while (fscanf(f, "%d %d %d %d %f", &mode, &ln, &lm, &tile, &ms) == 5)
+    g_tuned[std::make_tuple(mode, ln, lm)] = Tuned{tile, ms};
+  fclose(f);
+  return SEG_OK;
+}
+
+void seg_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
 }
 
 int seg_filter_pairs(const float* fibers, int64_t n, const float* centroids, int64_t m,

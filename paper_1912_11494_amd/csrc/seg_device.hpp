@@ -48,6 +48,26 @@ __device__ __forceinline__ uint32_t bits_below(uint64_t mask) {
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
+// Index j of the job holding work item `it`: the last j with
+// start[j] <= it (start is ascending, start[0] = 0).
+__device__ __forceinline__ int32_t find_job(const int64_t* __restrict__ start, int32_t njobs,
+                                            int64_t it) {
+  int32_t lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= it) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A value every lane holds equally, made visibly wave-uniform (kept in scalar
+// registers, so addresses derived from it use scalar loads).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 struct Point {
   float x, y, z;
 };

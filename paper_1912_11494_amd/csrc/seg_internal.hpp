@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace seg {
 
 constexpr unsigned int FLAG_BUNDLE = 1u;
@@ -24,11 +26,22 @@ struct PrefilterBuf {
   unsigned int* emax = nullptr;  // device max of the fiber quantisation error
 };
 
-// Library-owned batch scratch: work list and counters.
+// Library-owned batch scratch: the device job list and the last captured HIP
+// graph with the launch shape it was captured for.
 struct BatchBuf {
-  void* items = nullptr;
+  void* items = nullptr;  // job descriptors + prefix sums of work items
   size_t items_bytes = 0;
-  unsigned int* next = nullptr;
+  void* fib_feat = nullptr;  // quantised features of every subject of the batch
+  size_t fib_feat_bytes = 0;
+  float* fib_h = nullptr;
+  size_t fib_h_bytes = 0;
+  void* cen_feat = nullptr;  // column features + constants of every atlas
+  size_t cen_feat_bytes = 0;
+  hipStream_t cap = nullptr;  // private stream for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> key;  // launch shape of `exec`
+  int32_t njobs = 0;          // jobs in the uploaded list
 };
 
 // A prepared atlas as the batch path sees it.
@@ -63,6 +76,16 @@ int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,
                     unsigned long long* count, PrefilterBuf& pb, hipStream_t s);
+
+// Per-mode batch launches (seg_prefilter.hip / seg_kernels.hip): size the
+// buffers, upload the job list (synchronising `s` when the launch shape
+// changes) and run the whole batch as one cached HIP graph (seg_graph.hpp).
+int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
+                    const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
+                    int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s);
+int plain_batch(int cfg, const BatchAtlas* atlases, int32_t n_atlases, const float* const* fibers,
+                const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
+                float* const* dists, BatchBuf& bb, hipStream_t s);
 
 // Batched persistent launch (seg_batch.hip); same return codes.
 int run_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,

@@ -11,7 +11,12 @@
 //   labels/dists  caller's [N] int32 / float32
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "seg_device.hpp"
+#include "seg_graph.hpp"
 #include "seg_internal.hpp"
 
 namespace seg {
@@ -165,14 +170,29 @@ __global__ __launch_bounds__(256) void dense_kernel(const float* __restrict__ fi
 // lane (exact_pair); accepted pairs are merged into per-fiber 64-bit
 // (D, centroid) keys in LDS with an atomic minimum, which makes the result
 // independent of drain order.  Memory stays O(N + M): no N x M buffer exists.
+// One subject against one atlas, as the plain pass sees it.
+struct PlainJob {
+  const float* fibers;
+  int64_t n;
+  const float4* ccen;
+  const float* cprep;
+  int32_t m;
+  const int32_t* bid;
+  int32_t* labels;
+  float* dists;
+};
+
 template <int FPL, int QCAP, bool STATS>
-__global__ __launch_bounds__(256) void plain_kernel(const float* __restrict__ fibers, int64_t n,
-                                                    const float4* __restrict__ ccen,
-                                                    const float* __restrict__ cprep, int32_t m,
-                                                    const int32_t* __restrict__ bid,
-                                                    int32_t* __restrict__ labels,
-                                                    float* __restrict__ dists,
-                                                    unsigned long long* __restrict__ counters) {
+__device__ __forceinline__ void plain_block(const PlainJob& job, int64_t block,
+                                            unsigned long long* __restrict__ counters) {
+  const float* __restrict__ fibers = job.fibers;
+  const int64_t n = job.n;
+  const float4* __restrict__ ccen = job.ccen;
+  const float* __restrict__ cprep = job.cprep;
+  const int32_t m = job.m;
+  const int32_t* __restrict__ bid = job.bid;
+  int32_t* __restrict__ labels = job.labels;
+  float* __restrict__ dists = job.dists;
   static_assert(64 * FPL <= 256, "slot must fit 8 bits");
   static_assert(QCAP >= 2 * 64 * FPL, "queue must hold two centroids' worth");
   constexpr int WAVES = 4;
@@ -180,7 +200,7 @@ __global__ __launch_bounds__(256) void plain_kernel(const float* __restrict__ fi
   __shared__ uint64_t s_keys[WAVES][64 * FPL];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = threadIdx.x >> 6;
-  const int64_t wbase = ((int64_t)blockIdx.x * WAVES + wave) * (64 * FPL);
+  const int64_t wbase = (block * WAVES + wave) * (64 * FPL);
   WaveQueue wq{s_queue[wave], s_keys[wave]};
   StageCounts sc{counters};
 
@@ -245,6 +265,23 @@ __global__ __launch_bounds__(256) void plain_kernel(const float* __restrict__ fi
     const int64_t f = wbase + k * 64 + lane;
     if (f < n) write_result(wq.keys[k * 64 + lane], bid, labels + f, dists + f);
   }
+}
+
+template <int FPL, int QCAP, bool STATS>
+__global__ __launch_bounds__(256) void plain_kernel(PlainJob job,
+                                                    unsigned long long* __restrict__ counters) {
+  plain_block<FPL, QCAP, STATS>(job, blockIdx.x, counters);
+}
+
+// Batch form: one launch over the flattened work list (see
+// prefilter_batch_kernel); jobs are ordered by atlas size, largest first.
+template <int FPL, int QCAP>
+__global__ __launch_bounds__(256) void plain_batch_kernel(const PlainJob* __restrict__ jobs,
+                                                          const int64_t* __restrict__ job_start,
+                                                          int32_t njobs) {
+  const int64_t it = blockIdx.x;
+  const int32_t j = find_job(job_start, njobs, it);
+  plain_block<FPL, QCAP, false>(jobs[j], it - job_start[j], nullptr);
 }
 
 // Survivors of the center test as (fiber, centroid) pairs (diagnostics).
@@ -322,12 +359,11 @@ static void plain_launch(const float* fibers, int64_t n, const float4* ccen, con
   constexpr int per_block = 4 * 64 * FPL;
   const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
   constexpr int QCAP = 512;
+  const PlainJob job{fibers, n, ccen, cprep, m, bid, labels, dists};
   if (counters)
-    plain_kernel<FPL, QCAP, true><<<blocks, 256, 0, s>>>(fibers, n, ccen, cprep, m, bid, labels,
-                                                         dists, counters);
+    plain_kernel<FPL, QCAP, true><<<blocks, 256, 0, s>>>(job, counters);
   else
-    plain_kernel<FPL, QCAP, false><<<blocks, 256, 0, s>>>(fibers, n, ccen, cprep, m, bid, labels,
-                                                          dists, counters);
+    plain_kernel<FPL, QCAP, false><<<blocks, 256, 0, s>>>(job, counters);
 }
 
 int plain_default_cfg(int64_t n) {
@@ -349,6 +385,108 @@ int launch_plain(const float* fibers, int64_t n, const float4* ccen, const float
     default: return -2;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+namespace {
+
+int grow_buf(void** p, size_t* have, size_t want) {
+  if (want <= *have) return 0;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  if (hipMalloc(p, want) != hipSuccess) return -3;
+  *have = want;
+  return 0;
+}
+
+template <int FPL>
+int plain_batch_cfg(int cfg, const BatchAtlas* at, int32_t na, const float* const* fibers,
+                    const int64_t* nf, int32_t ns, int32_t* const* labels, float* const* dists,
+                    BatchBuf& bb, hipStream_t s) {
+  constexpr int QCAP = 512;
+  constexpr int64_t FPB = 4 * 64 * FPL;
+  std::vector<uint64_t> key = {1u, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns};
+  for (int32_t a = 0; a < na; ++a) {
+    key.push_back((uint64_t)(uintptr_t)at[a].ccen);
+    key.push_back((uint64_t)at[a].m);
+  }
+  for (int32_t i = 0; i < ns; ++i) {
+    key.push_back((uint64_t)(uintptr_t)fibers[i]);
+    key.push_back((uint64_t)nf[i]);
+    for (int32_t a = 0; a < na; ++a) {
+      key.push_back((uint64_t)(uintptr_t)labels[i * na + a]);
+      key.push_back((uint64_t)(uintptr_t)dists[i * na + a]);
+    }
+  }
+  if (!(bb.exec && bb.key == key)) {
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    std::vector<int32_t> order(na);
+    for (int32_t a = 0; a < na; ++a) order[a] = a;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return at[x].m > at[y].m; });
+    std::vector<PlainJob> jobs;
+    std::vector<int64_t> start(1, 0);
+    for (int32_t oi = 0; oi < na; ++oi) {
+      const int32_t a = order[oi];
+      if (at[a].m == 0) continue;
+      for (int32_t i = 0; i < ns; ++i) {
+        if (nf[i] == 0) continue;
+        jobs.push_back(PlainJob{fibers[i], nf[i], at[a].ccen, at[a].cprep, at[a].m, at[a].bid,
+                                labels[i * na + a], dists[i * na + a]});
+        start.push_back(start.back() + (nf[i] + FPB - 1) / FPB);
+      }
+    }
+    const size_t need = 256 + jobs.size() * sizeof(PlainJob) + start.size() * sizeof(int64_t);
+    int rc = grow_buf(&bb.items, &bb.items_bytes, need);
+    if (rc) return rc;
+    std::vector<uint8_t> host(need - 256);
+    if (!jobs.empty()) memcpy(host.data(), jobs.data(), jobs.size() * sizeof(PlainJob));
+    memcpy(host.data() + jobs.size() * sizeof(PlainJob), start.data(),
+           start.size() * sizeof(int64_t));
+    if (hipMemcpy((uint8_t*)bb.items + 256, host.data(), host.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return -1;
+    bb.key.clear();
+    bb.njobs = (int32_t)jobs.size();
+  }
+  const PlainJob* djobs = (const PlainJob*)((uint8_t*)bb.items + 256);
+  const int64_t* dstart = (const int64_t*)((uint8_t*)bb.items + 256 + bb.njobs * sizeof(PlainJob));
+  const int32_t njobs = bb.njobs;
+  int64_t total = 0;  // work items (fiber blocks over all jobs)
+  for (int32_t a = 0; a < na; ++a)
+    if (at[a].m > 0)
+      for (int32_t i = 0; i < ns; ++i) total += (nf[i] + FPB - 1) / FPB;
+  auto enqueue = [&](hipStream_t cs) -> int {
+    for (int32_t a = 0; a < na; ++a)
+      if (at[a].m == 0)
+        for (int32_t i = 0; i < ns; ++i)
+          if (launch_fill_empty(nf[i], labels[i * na + a], dists[i * na + a], cs)) return -1;
+    if (njobs > 0 && total > 0)
+      plain_batch_kernel<FPL, QCAP><<<(unsigned)total, 256, 0, cs>>>(djobs, dstart, njobs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  };
+  return graph_launch(bb, key, s, enqueue);
+}
+
+}  // namespace
+
+int plain_batch(int cfg, const BatchAtlas* atlases, int32_t n_atlases, const float* const* fibers,
+                const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
+                float* const* dists, BatchBuf& bb, hipStream_t s) {
+  switch (cfg) {
+    case 0:
+    case 4:
+      return plain_batch_cfg<4>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
+                                dists, bb, s);
+    case 1:
+      return plain_batch_cfg<1>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
+                                dists, bb, s);
+    case 2:
+      return plain_batch_cfg<2>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
+                                dists, bb, s);
+    default:
+      return -2;
+  }
 }
 
 int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32_t m,

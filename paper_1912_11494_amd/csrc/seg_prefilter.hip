@@ -39,7 +39,12 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "seg_device.hpp"
+#include "seg_graph.hpp"
 #include "seg_internal.hpp"
 
 namespace seg {
@@ -427,6 +432,21 @@ template <> struct Frag<Q_FP8> {
   }
 };
 
+// One subject against one atlas, as the fused kernel sees it.
+struct PfJob {
+  const uint8_t* ffeat;  // quantised fiber features [n_pad][KP]
+  const float* fnegh;    // -Ha per fiber row [n_pad]
+  const uint8_t* cfeat;  // quantised column features [ncols_pad][KP]
+  const float* cbias;    // cb per column [ncols_pad]
+  int32_t ncols_pad;
+  const float* fibers;   // the subject's fiber records
+  int64_t n;
+  const float* cprep;    // prepared centroid records (63 coordinates + T2)
+  const int32_t* bid;
+  int32_t* labels;
+  float* dists;
+};
+
 // Largest of a lane's 16 outputs as a tree of three-input maxima (depth 3,
 // so the reduction does not serialise on one dependency chain).
 __device__ __forceinline__ float max16(const f32x16& a) {
@@ -466,12 +486,20 @@ template <int KP> struct Chunk { static constexpr int CH = KP <= 32 ? 8 : (KP <=
 // the plain pass.  With PAIRS, survivors are written to a global list instead
 // (diagnostics).
 template <int Q, int KP, int GF, int CPC, bool STATS, bool PAIRS>
-__global__ __launch_bounds__(256) void prefilter_kernel(
-    const uint8_t* __restrict__ ffeat, const float* __restrict__ fnegh,
-    const uint8_t* __restrict__ cfeat, const float* __restrict__ cbias, int32_t ncols_pad,
-    const float* __restrict__ fibers, int64_t n, const float* __restrict__ cprep,
-    const int32_t* __restrict__ bid, int32_t* __restrict__ labels, float* __restrict__ dists,
-    unsigned long long* __restrict__ counters, int32_t* __restrict__ pairs, int64_t cap) {
+__device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
+                                                unsigned long long* __restrict__ counters,
+                                                int32_t* __restrict__ pairs, int64_t cap) {
+  const uint8_t* __restrict__ ffeat = job.ffeat;
+  const float* __restrict__ fnegh = job.fnegh;
+  const uint8_t* __restrict__ cfeat = job.cfeat;
+  const float* __restrict__ cbias = job.cbias;
+  const int32_t ncols_pad = job.ncols_pad;
+  const float* __restrict__ fibers = job.fibers;
+  const int64_t n = job.n;
+  const float* __restrict__ cprep = job.cprep;
+  const int32_t* __restrict__ bid = job.bid;
+  int32_t* __restrict__ labels = job.labels;
+  float* __restrict__ dists = job.dists;
   using FT = typename Frag<Q>::T;
   constexpr int KS = KP / 16;
   constexpr int EB = QTraits<Q>::bytes;
@@ -496,7 +524,7 @@ __global__ __launch_bounds__(256) void prefilter_kernel(
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int half = lane >> 5;
-  const int64_t wbase = ((int64_t)blockIdx.x * WAVES + wave) * FPW;
+  const int64_t wbase = (block * WAVES + wave) * FPW;
   WaveQueue wq{PAIRS ? nullptr : s_queue[wave], PAIRS ? nullptr : s_keys[wave]};
   StageCounts sc{counters};
 
@@ -676,6 +704,28 @@ __global__ __launch_bounds__(256) void prefilter_kernel(
   }
 }
 
+template <int Q, int KP, int GF, int CPC, bool STATS, bool PAIRS>
+__global__ __launch_bounds__(256) void prefilter_kernel(PfJob job,
+                                                        unsigned long long* __restrict__ counters,
+                                                        int32_t* __restrict__ pairs, int64_t cap) {
+  prefilter_block<Q, KP, GF, CPC, STATS, PAIRS>(job, blockIdx.x, counters, pairs, cap);
+}
+
+// Batch form: one launch over the flattened work list.  Block b runs fiber
+// block b - start[j] of job j; jobs are ordered by cost per block (largest
+// atlas first), and the hardware dispatches blocks in index order as CUs
+// free up, so the costliest items start first and the cheapest fill the
+// tail.  (A persistent loop pulling items from a counter needs about 100
+// more registers per lane here and runs at half the occupancy.)
+template <int Q, int KP, int GF, int CPC>
+__global__ __launch_bounds__(256) void prefilter_batch_kernel(const PfJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ job_start,
+                                                              int32_t njobs) {
+  const int64_t it = blockIdx.x;
+  const int32_t j = find_job(job_start, njobs, it);
+  prefilter_block<Q, KP, GF, CPC, false, false>(jobs[j], it - job_start[j], nullptr, nullptr, 0);
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -754,21 +804,20 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
   pf_column_kernel<Q, MAPK, KP><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
       cprep, m, ncols_pad, prm, cfeat, cb);
   const unsigned blocks = (unsigned)(n_pad / FPB);
+  const PfJob job{(const uint8_t*)pb.fib_feat, pb.fib_h, cfeat, cb, ncols_pad, fibers, n, cprep,
+                  bid, labels, dists};
   if (pairs) {
-    prefilter_kernel<Q, KP, GF, MI::CPC, false, true><<<blocks, 256, 0, s>>>(
-        (const uint8_t*)pb.fib_feat, pb.fib_h, cfeat, cb, ncols_pad, fibers, n, cprep, bid,
-        labels, dists, counters, pairs, cap);
+    prefilter_kernel<Q, KP, GF, MI::CPC, false, true><<<blocks, 256, 0, s>>>(job, counters, pairs,
+                                                                             cap);
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return -1;
   if (counters)
-    prefilter_kernel<Q, KP, GF, MI::CPC, true, false><<<blocks, 256, 0, s>>>(
-        (const uint8_t*)pb.fib_feat, pb.fib_h, cfeat, cb, ncols_pad, fibers, n, cprep, bid,
-        labels, dists, counters, nullptr, 0);
+    prefilter_kernel<Q, KP, GF, MI::CPC, true, false><<<blocks, 256, 0, s>>>(job, counters,
+                                                                             nullptr, 0);
   else
-    prefilter_kernel<Q, KP, GF, MI::CPC, false, false><<<blocks, 256, 0, s>>>(
-        (const uint8_t*)pb.fib_feat, pb.fib_h, cfeat, cb, ncols_pad, fibers, n, cprep, bid,
-        labels, dists, counters, nullptr, 0);
+    prefilter_kernel<Q, KP, GF, MI::CPC, false, false><<<blocks, 256, 0, s>>>(job, counters,
+                                                                              nullptr, 0);
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -807,7 +856,155 @@ int dispatch(const Cfg& c, const float* fibers, int64_t n, const float* cprep, i
   return -2;
 }
 
+// A batch: every subject against every atlas with one shared frame (origin,
+// scale) and one fiber error bound, so each subject's features are computed
+// once for all atlases.  Launched as one persistent kernel inside a cached
+// HIP graph.
+template <int Q, int MAPK, int KP, int GF>
+int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* const* fibers,
+              const int64_t* nf, int32_t ns, int32_t* const* labels, float* const* dists,
+              BatchBuf& bb, hipStream_t s) {
+  using MI = MapInfo<MAPK, KP>;
+  constexpr int EB = QTraits<Q>::bytes;
+  constexpr int FPB = 4 * GF * 32;
+  constexpr int CC = 32 * Chunk<KP>::CH;
+  constexpr size_t HDR = 512;  // PfParams at the head of the job buffer
+  std::vector<uint64_t> key = {2u, (uint64_t)mode, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns};
+  for (int32_t a = 0; a < na; ++a) {
+    key.push_back((uint64_t)(uintptr_t)at[a].cprep);
+    key.push_back((uint64_t)at[a].m);
+  }
+  for (int32_t i = 0; i < ns; ++i) {
+    key.push_back((uint64_t)(uintptr_t)fibers[i]);
+    key.push_back((uint64_t)nf[i]);
+    for (int32_t a = 0; a < na; ++a) {
+      key.push_back((uint64_t)(uintptr_t)labels[i * na + a]);
+      key.push_back((uint64_t)(uintptr_t)dists[i * na + a]);
+    }
+  }
+  std::vector<int64_t> foff(ns), npad(ns);
+  int64_t ftot = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    npad[i] = (nf[i] + FPB - 1) / FPB * FPB;
+    foff[i] = ftot;
+    ftot += npad[i];
+  }
+  std::vector<int64_t> coff(na);
+  std::vector<int32_t> ncp(na);
+  int64_t ctot = 0;
+  for (int32_t a = 0; a < na; ++a) {
+    ncp[a] = (at[a].m * MI::CPC + CC - 1) / CC * CC;
+    coff[a] = ctot;
+    ctot += ncp[a];
+  }
+  // jobs: atlases with more columns first (costlier blocks early), then subjects
+  std::vector<int32_t> order(na);
+  for (int32_t a = 0; a < na; ++a) order[a] = a;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ncp[x] > ncp[y]; });
+  const bool same = bb.exec && bb.key == key;
+  uint8_t* items = (uint8_t*)bb.items;
+  if (!same) {
+    // buffers may be in use by a previous launch on this stream
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    int rc = grow(&bb.fib_feat, &bb.fib_feat_bytes, (size_t)std::max<int64_t>(ftot, 1) * KP * EB);
+    rc = rc ? rc : grow((void**)&bb.fib_h, &bb.fib_h_bytes, (size_t)std::max<int64_t>(ftot, 1) * 4);
+    rc = rc ? rc : grow(&bb.cen_feat, &bb.cen_feat_bytes,
+                        (size_t)std::max<int64_t>(ctot, 1) * (KP * EB + 4));
+    if (rc) return rc;
+    std::vector<PfJob> jobs;
+    std::vector<int64_t> start(1, 0);
+    uint8_t* cfeat = (uint8_t*)bb.cen_feat;
+    float* cbb = (float*)(cfeat + (size_t)ctot * KP * EB);
+    for (int32_t oi = 0; oi < na; ++oi) {
+      const int32_t a = order[oi];
+      if (at[a].m == 0) continue;
+      for (int32_t i = 0; i < ns; ++i) {
+        if (nf[i] == 0) continue;
+        jobs.push_back(PfJob{(const uint8_t*)bb.fib_feat + (size_t)foff[i] * KP * EB,
+                             bb.fib_h + foff[i], cfeat + (size_t)coff[a] * KP * EB,
+                             cbb + coff[a], ncp[a], fibers[i], nf[i], at[a].cprep, at[a].bid,
+                             labels[i * na + a], dists[i * na + a]});
+        start.push_back(start.back() + npad[i] / FPB);
+      }
+    }
+    const size_t need = HDR + jobs.size() * sizeof(PfJob) + start.size() * sizeof(int64_t);
+    rc = grow(&bb.items, &bb.items_bytes, need);
+    if (rc) return rc;
+    items = (uint8_t*)bb.items;
+    std::vector<uint8_t> host(need - HDR);
+    if (!jobs.empty()) memcpy(host.data(), jobs.data(), jobs.size() * sizeof(PfJob));
+    memcpy(host.data() + jobs.size() * sizeof(PfJob), start.data(), start.size() * sizeof(int64_t));
+    if (hipMemcpy(items + HDR, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return -1;
+    bb.key.clear();  // stale until the new graph is captured
+    bb.njobs = (int32_t)jobs.size();
+  }
+  static_assert(sizeof(PfParams) <= HDR, "parameters fit the header of the job buffer");
+  PfParams* prm = (PfParams*)items;
+  const PfJob* djobs = (const PfJob*)(items + HDR);
+  const int64_t* dstart = (const int64_t*)(items + HDR + bb.njobs * sizeof(PfJob));
+  const int32_t njobs = bb.njobs;
+  int64_t total = 0;  // work items (fiber blocks over all jobs)
+  for (int32_t a = 0; a < na; ++a)
+    if (at[a].m > 0)
+      for (int32_t i = 0; i < ns; ++i) total += npad[i] / FPB;
+  auto enqueue = [&](hipStream_t cs) -> int {
+    uint8_t* cfeat = (uint8_t*)bb.cen_feat;
+    float* cbb = (float*)(cfeat + (size_t)ctot * KP * EB);
+    pf_init_kernel<<<1, 64, 0, cs>>>(prm);
+    for (int32_t a = 0; a < na; ++a)
+      if (at[a].m > 0)
+        pf_bbox_kernel<<<(unsigned)((at[a].m + 255) / 256), 256, 0, cs>>>(at[a].cprep, at[a].m, prm);
+    for (int32_t i = 0; i < ns; ++i)
+      if (nf[i] > 0)
+        pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)(npad[i] / 64), 64, 0, cs>>>(
+            fibers[i], nf[i], npad[i], prm, (uint8_t*)bb.fib_feat + (size_t)foff[i] * KP * EB,
+            bb.fib_h + foff[i]);
+    for (int32_t a = 0; a < na; ++a) {
+      if (at[a].m > 0) {
+        pf_column_kernel<Q, MAPK, KP><<<(unsigned)((ncp[a] + 255) / 256), 256, 0, cs>>>(
+            at[a].cprep, at[a].m, ncp[a], prm, cfeat + (size_t)coff[a] * KP * EB, cbb + coff[a]);
+      } else {
+        for (int32_t i = 0; i < ns; ++i)
+          if (launch_fill_empty(nf[i], labels[i * na + a], dists[i * na + a], cs)) return -1;
+      }
+    }
+    if (njobs > 0 && total > 0)
+      prefilter_batch_kernel<Q, KP, GF, MI::CPC><<<(unsigned)total, 256, 0, cs>>>(djobs, dstart,
+                                                                                  njobs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  };
+  return graph_launch(bb, key, s, enqueue);
+}
+
+int batch_dispatch(int mode, int cfg, const Cfg& c, const BatchAtlas* at, int32_t na,
+                   const float* const* fibers, const int64_t* nf, int32_t ns,
+                   int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s) {
+#define SEG_PFB(QQ, MM, KK, GG)                                                             \
+  if (c.q == QQ && c.mapk == MM && c.kp == KK && c.gf == GG)                                \
+    return batch_cfg<QQ, MM, KK, GG>(mode, cfg, at, na, fibers, nf, ns, labels, dists, bb, s);
+  SEG_PFB(Q_BF16, MAP_SYM, 16, 2)
+  SEG_PFB(Q_BF16, MAP_SYM, 16, 1)
+  SEG_PFB(Q_BF16, MAP_SYM, 32, 2)
+  SEG_PFB(Q_F16, MAP_SYM, 16, 2)
+  SEG_PFB(Q_F16, MAP_SYM, 16, 1)
+  SEG_PFB(Q_F16, MAP_SYM, 32, 2)
+  SEG_PFB(Q_FP8, MAP_SYM, 16, 2)
+  SEG_PFB(Q_BF16, MAP_ORIENTED, 64, 2)
+#undef SEG_PFB
+  return -2;
+}
+
 }  // namespace
+
+int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
+                    const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
+                    int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s) {
+  Cfg c;
+  if (resolve(mode, cfg, &c)) return -2;
+  return batch_dispatch(mode, cfg, c, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
+                        dists, bb, s);
+}
 
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,

@@ -95,6 +95,13 @@ def lib():
         L.seg_filter_pairs.restype = ctypes.c_int
         L.seg_query_stats.argtypes = [ctypes.POINTER(Stats)]
         L.seg_query_stats.restype = ctypes.c_int
+        L.seg_autotune.argtypes = [P, P, i64, i32, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_float), P]
+        L.seg_autotune.restype = ctypes.c_int
+        L.seg_tune_save.argtypes = [ctypes.c_char_p]
+        L.seg_tune_save.restype = ctypes.c_int
+        L.seg_tune_load.argtypes = [ctypes.c_char_p]
+        L.seg_tune_load.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -257,3 +264,27 @@ def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mo
     rc = lib().seg_segment_batch(ah, na, fp, nf, ns, lp, dp, ctypes.byref(opt), _stream(stream))
     _check(rc)
     return outs
+
+
+def autotune(atlas: "Atlas", fibers: torch.Tensor, mode="bf16", reps: int = 3, stream=None):
+    """Time every kernel configuration of `mode` on these inputs and remember
+    the fastest for later calls with tile=0; returns (tile, ms)."""
+    _dev(fibers, torch.float32, (21, 3), "fibers")
+    best = ctypes.c_int32(0)
+    ms = ctypes.c_float(0.0)
+    rc = lib().seg_autotune(atlas.handle, fibers.data_ptr(), fibers.shape[0], _mode(mode), reps,
+                            ctypes.byref(best), ctypes.byref(ms), _stream(stream))
+    _check(rc)
+    return int(best.value), float(ms.value)
+
+
+def tune_save(path: str):
+    _check(lib().seg_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(lib().seg_tune_load(path.encode()))
+
+
+def tune_clear():
+    lib().seg_tune_clear()

@@ -242,21 +242,39 @@ def _fiber_chunk(atlases: Sequence[Atlas], matched: Sequence[float], sigma: floa
     return allf.astype(np.float32)
 
 
+def _chunk_job(args):
+    atlases, subject, seed, subject_idx, c = args
+    lo = c * CHUNK
+    n = min(CHUNK, subject.n_fibers - lo)
+    return _fiber_chunk(atlases, subject.matched, subject.sigma, n,
+                        _rng(seed, 1, subject_idx, c))
+
+
 def make_fibers(atlases: Sequence[Atlas], subject: SubjectSpec, seed: int,
-                subject_idx: int = 0, start: int = 0,
-                count: Optional[int] = None) -> np.ndarray:
-    """Fibers [start, start+count) of a subject, float32 [count, 21, 3]."""
+                subject_idx: int = 0, start: int = 0, count: Optional[int] = None,
+                workers: int = 1) -> np.ndarray:
+    """Fibers [start, start+count) of a subject, float32 [count, 21, 3].
+
+    ``workers`` > 1 draws the chunks in a pool of forked processes (same
+    output); call it before the process has touched the GPU.
+    """
     if count is None:
         count = subject.n_fibers - start
     if start < 0 or count < 0 or start + count > subject.n_fibers:
         raise ValueError("fiber range outside the subject")
     out = np.empty((count, N_POINTS, 3), np.float32)
     c0, c1 = start // CHUNK, (start + count + CHUNK - 1) // CHUNK
-    for c in range(c0, c1):
+    jobs = [(atlases, subject, seed, subject_idx, c) for c in range(c0, c1)]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+            chunks = pool.map(_chunk_job, jobs, chunksize=1)
+    else:
+        chunks = map(_chunk_job, jobs)
+    for c, chunk in zip(range(c0, c1), chunks):
         lo = c * CHUNK
-        n = min(CHUNK, subject.n_fibers - lo)
-        rng = _rng(seed, 1, subject_idx, c)
-        chunk = _fiber_chunk(atlases, subject.matched, subject.sigma, n, rng)
+        n = chunk.shape[0]
         a = max(start, lo)
         b = min(start + count, lo + n)
         out[a - start:b - start] = chunk[a - lo:b - lo]

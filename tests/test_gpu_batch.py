@@ -1,0 +1,170 @@
+"""GPU parity of the batched path (persistent launch inside a cached HIP graph)
+and of the autotuner, through the C ABI."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def seg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need the GPU"
+    import paper_1912_11494_amd as P
+
+    P.lib()
+    return P
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _atlases():
+    long_ = synth.make_atlas(synth.AtlasSpec(6, 9, 80.0, 200.0, 6.0, 12.0), 501)
+    short = synth.make_atlas(synth.AtlasSpec(11, 10, 20.0, 80.0, 5.0, 8.0), 502)
+    return [long_, short]
+
+
+def _subjects(atl, sizes, seed):
+    subs = []
+    for i, n in enumerate(sizes):
+        spec = synth.SubjectSpec(n, 2.0, (0.2, 0.2))
+        subs.append(synth.make_fibers(atl, spec, seed, subject_idx=i) if n else
+                    np.zeros((0, 21, 3), np.float32))
+    return subs
+
+
+def _gpu_atlas(seg, at):
+    import torch
+
+    d = torch.device("cuda:0")
+    return seg.Atlas(torch.from_numpy(at.centroids).to(d), torch.from_numpy(at.bundle_id).to(d),
+                     torch.from_numpy(at.thresholds).to(d))
+
+
+@pytest.mark.parametrize("mode", ["plain", "bf16", "fp16", "bf16_oriented"])
+def test_batch_matches_oracle(seg, mode):
+    import torch
+
+    atl = _atlases()
+    subs = _subjects(atl, [1500, 0, 257, 3001, 64, 777], seed=77)
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    gf = [torch.from_numpy(f).to(d) for f in subs]
+    log(f"batch mode={mode}")
+    outs = seg.segment_batch(ga, gf, mode=mode)
+    torch.cuda.synchronize()
+    for i, f in enumerate(subs):
+        for a, at in enumerate(atl):
+            lab = outs[i][a][0].cpu().numpy()
+            dist = outs[i][a][1].cpu().numpy()
+            if len(f) == 0:
+                assert lab.size == 0
+                continue
+            l32, d32, _ = oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)
+            assert np.array_equal(lab, l32), (mode, i, a)
+            assert np.array_equal(dist, d32), (mode, i, a)
+            # the batch equals the one-subject call
+            l1, d1 = ga[a].segment(gf[i], mode=mode)
+            assert torch.equal(l1.cpu(), outs[i][a][0].cpu())
+
+
+def test_batch_graph_replay_and_reshape(seg):
+    import torch
+
+    atl = _atlases()
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    subs = _subjects(atl, [900, 1300], seed=5)
+    gf = [torch.from_numpy(f).to(d) for f in subs]
+    outs = [[(torch.empty(len(f), dtype=torch.int32, device=d),
+              torch.empty(len(f), dtype=torch.float32, device=d)) for _ in atl] for f in subs]
+    want = [[oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)[0] for at in atl]
+            for f in subs]
+    for rep in range(4):
+        log(f"replay {rep}")
+        for o in outs:
+            for lab, dist in o:
+                lab.fill_(-7)
+        seg.segment_batch(ga, gf, mode="bf16", outs=outs)
+        torch.cuda.synchronize()
+        # eager work between replays
+        l_e, _ = ga[0].segment(gf[0], mode="plain")
+        torch.cuda.synchronize()
+        assert np.array_equal(l_e.cpu().numpy(), want[0][0])
+        for i in range(2):
+            for a in range(2):
+                assert np.array_equal(outs[i][a][0].cpu().numpy(), want[i][a]), (rep, i, a)
+    # new data in the same buffers: the replay must read it
+    new = _subjects(atl, [900, 1300], seed=6)
+    for g, f in zip(gf, new):
+        g.copy_(torch.from_numpy(f).to(d))
+    seg.segment_batch(ga, gf, mode="bf16", outs=outs)
+    torch.cuda.synchronize()
+    for i, f in enumerate(new):
+        for a, at in enumerate(atl):
+            l32 = oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)[0]
+            assert np.array_equal(outs[i][a][0].cpu().numpy(), l32)
+    # another shape: recaptured
+    subs3 = _subjects(atl, [300, 50, 1200], seed=8)
+    gf3 = [torch.from_numpy(f).to(d) for f in subs3]
+    outs3 = seg.segment_batch(ga, gf3, mode="plain")
+    torch.cuda.synchronize()
+    for i, f in enumerate(subs3):
+        for a, at in enumerate(atl):
+            l32 = oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)[0]
+            assert np.array_equal(outs3[i][a][0].cpu().numpy(), l32)
+
+
+def test_batch_empty_atlas(seg):
+    import torch
+
+    atl = _atlases()
+    d = torch.device("cuda:0")
+    empty = seg.Atlas(torch.zeros((0, 21, 3), dtype=torch.float32, device=d),
+                      torch.zeros(0, dtype=torch.int32, device=d),
+                      torch.ones(1, dtype=torch.float32, device=d))
+    assert len(empty) == 0
+    subs = _subjects(atl, [400], seed=9)
+    gf = [torch.from_numpy(subs[0]).to(d)]
+    outs = seg.segment_batch([empty, _gpu_atlas(seg, atl[1])], gf, mode="bf16")
+    torch.cuda.synchronize()
+    assert (outs[0][0][0] == -1).all() and torch.isinf(outs[0][0][1]).all()
+    l32 = oracle.segment_f32(subs[0], atl[1].centroids, atl[1].bundle_id, atl[1].thresholds)[0]
+    assert np.array_equal(outs[0][1][0].cpu().numpy(), l32)
+
+
+def test_autotune_roundtrip(seg, tmp_path):
+    import torch
+
+    atl = _atlases()
+    d = torch.device("cuda:0")
+    ga = _gpu_atlas(seg, atl[1])
+    subs = _subjects(atl, [5000], seed=10)
+    f = torch.from_numpy(subs[0]).to(d)
+    seg.tune_clear()
+    for mode in ("plain", "bf16", "dense"):
+        tile, ms = seg.autotune(ga, f, mode=mode, reps=2)
+        log(f"autotune {mode}: tile {tile} {ms:.3f} ms")
+        assert tile > 0 and ms > 0
+        lab, dist = ga.segment(f, mode=mode)  # tile 0 now resolves to the tuned tile
+        torch.cuda.synchronize()
+        l32, d32, _ = oracle.segment_f32(subs[0], atl[1].centroids, atl[1].bundle_id,
+                                         atl[1].thresholds)
+        assert np.array_equal(lab.cpu().numpy(), l32)
+    path = str(tmp_path / "tune.txt")
+    seg.tune_save(path)
+    lines = open(path).read().split("\n")
+    assert len([x for x in lines if x.strip()]) == 3
+    seg.tune_clear()
+    seg.tune_load(path)
+    seg.tune_clear()
