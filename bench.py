@@ -34,11 +34,18 @@ PEAK_BF16 = 2500.0  # TFLOP/s dense MFMA
 PEAK_FP8 = 5000.0
 PEAK_HBM = 8000.0   # GB/s
 WORKLOADS = {
-    1: "20,000 fibers x 800 centroids (40 bundles x 20), 21 pts fp32",
-    2: "1,000,000 fibers x 3,600 centroids (36 bundles x 100), 21 pts fp32",
-    3: "4,145,000 fibers x 10,000 centroids (100 bundles x 100, 20-80 mm), 21 pts fp32",
-    4: "10,000,000 fibers x 20,000 centroids (200 bundles x 100), 21 pts fp32",
+    "small-20k-x-800": "20,000 fibers x 800 centroids (40 bundles x 20), 21 pts fp32",
+    "exact-1M-x-3600": "1,000,000 fibers x 3,600 centroids (36 bundles x 100), 21 pts fp32",
+    "paper-4145k-x-10k": "4,145,000 fibers x 10,000 centroids (100 bundles x 100, 20-80 mm), "
+                         "21 pts fp32",
+    "large-10M-x-20k": "10,000,000 fibers x 20,000 centroids (200 bundles x 100), 21 pts fp32",
 }
+# kernels whose HBM traffic is summarised: counter-file kernel-name prefix -> key
+TRAFFIC_KERNELS = [("seg::prefilter_kernel<0,", "prefilter_kernel:bf16"),
+                   ("seg::prefilter_kernel<1,", "prefilter_kernel:fp16"),
+                   ("seg::prefilter_kernel<2,", "prefilter_kernel:fp8"),
+                   ("seg::plain_kernel<", "plain_kernel"),
+                   ("seg::dense_kernel<1>", "dense_kernel")]
 KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
                   "paper_1912_11494_amd/csrc/seg_kernels.hip",
                   "paper_1912_11494_amd/csrc/seg_prefilter.hip"]
@@ -99,6 +106,51 @@ def traffic_for(kernel: str):
     return e.get("bytes_per_launch")
 
 
+def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
+    """Summarise two rocprofv3 --pmc runs of this script with --copy-probe
+    (FETCH_SIZE, then WRITE_SIZE) into HBM bytes per launch.  The 1 GiB device
+    copy in the same runs fixes the byte value of one counted KiB."""
+    import collections
+    import csv
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copies = [k for k in fe if "copy" in k.lower()]
+    if not copies:
+        raise SystemExit("no copy kernel in the counter file: run with --copy-probe")
+    big = max(copies, key=lambda k: max(fe[k]))
+    gib = float(1 << 30)
+    cf = gib / (max(fe[big]) * 1024.0)
+    cw = gib / (max(wr[big]) * 1024.0)
+    out = {"calibration": {"kernel": big, "fetch_kib": max(fe[big]), "write_kib": max(wr[big]),
+                           "bytes_per_kib_fetch": cf, "bytes_per_kib_write": cw,
+                           "note": "a 1 GiB device copy (reads 1 GiB, writes 1 GiB) fixes "
+                                   "the byte value of one counted KiB"}}
+    for prefix, key in TRAFFIC_KERNELS:
+        # the launch that bench.py times: statistics off (template flag false)
+        ks = [k for k in fe if k.replace(" ", "").startswith("void" + prefix.replace(" ", ""))
+              and "true" not in k]
+        if not ks:
+            continue
+        k = ks[0]
+        f = sum(fe[k]) / len(fe[k])
+        w = sum(wr.get(k, [0.0])) / max(1, len(wr.get(k, [0.0])))
+        out[key] = {"kernel": k, "fetch_kib": f, "write_kib": w,
+                    "bytes_per_launch": f * 1024.0 * cf + w * 1024.0 * cw,
+                    "source_hash": source_hash()}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    log(f"wrote {out_path}")
+
+
 def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
     import torch
 
@@ -148,13 +200,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--workload", default="paper-4145k-x-10k", choices=list(WORKLOADS))
     ap.add_argument("--mode", default=None, help="headline mode (default: fastest built)")
     ap.add_argument("--compare", default="plain,dense,bf16,fp16,bf16_oriented,fp8")
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
-                    help="fibers of the workload the CPU oracle is timed on")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="fibers of the workload the CPU oracle is timed on (0: all)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="only summarise two rocprofv3 counter files into profiles/traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,12 +226,12 @@ def main():
 
     import synth
 
-    cfg = args.config
-    at = synth.config_atlases(cfg)[0]
-    subj = synth.config_subjects(cfg)[0]
+    wl = args.workload
+    at = synth.workload_atlases(wl)[0]
+    subj = synth.workload_subjects(wl)[0]
     t0 = time.time()
-    fib = synth.make_fibers([at], subj, synth.fibers.config_seed(cfg))
-    log(f"generated config {cfg}: {fib.shape[0]} fibers x {at.n_centroids} centroids "
+    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=16)
+    log(f"generated {wl}: {fib.shape[0]} fibers x {at.n_centroids} centroids "
         f"in {time.time() - t0:.1f}s")
 
     import torch
@@ -186,6 +245,15 @@ def main():
     b = torch.from_numpy(at.bundle_id).to(d)
     t = torch.from_numpy(at.thresholds).to(d)
     N, M = fib.shape[0], at.n_centroids
+
+    if args.copy_probe:
+        # a copy of known size: reads 1 GiB and writes 1 GiB per launch
+        src = torch.empty(1 << 28, dtype=torch.float32, device=d).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     modes = {}
     outs = {}
@@ -228,11 +296,14 @@ def main():
     else:
         bound, kname = "mfma", "prefilter_kernel"
         peak = PEAK_FP8 if head == "fp8" else PEAK_BF16
-        kf = {"bf16": 16, "fp16": 16, "fp8": 16, "bf16_oriented": 128}.get(head, 16)
+        # algorithmic width of the product: 15 features (symmetric map, 4
+        # point groups) or 2 orders x 63 coordinates (oriented map)
+        kf = {"bf16_oriented": 126}.get(head, 15)
         ach = alg_flops(head, r["stats"], N, M, kf) / (r["kernel_ms"] * 1e-3) / 1e12
         dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head, "bf16+f32")
+    tkey = kname if head in ("dense", "plain") else f"{kname}:{head}"
     roofline = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": traffic_for(kname), "kernel": kname,
+                "frac": ach / peak, "traffic": traffic_for(tkey), "kernel": kname,
                 "kernel_ms": r["kernel_ms"]}
     if "dense" in modes:
         dm = modes["dense"]
@@ -241,19 +312,19 @@ def main():
                                          "frac": a_d / PEAK_FP32, "kernel_ms": dm["kernel_ms"]}
 
     cpu = None
-    if not args.no_cpu and args.cpu_sample > 0:
+    if not args.no_cpu:
         import oracle
 
-        ns = min(args.cpu_sample, N)
+        ns = N if args.cpu_sample <= 0 else min(args.cpu_sample, N)
         thr = oracle.get().max_threads()
         h0 = time.perf_counter()
         l_cpu, d_cpu, _ = oracle.segment_f32(fib[:ns], at.centroids, at.bundle_id, at.thresholds,
                                             mode=oracle.CUT, threads=thr)
         dt = time.perf_counter() - h0
         cpu = {"value": ns * M / dt, "unit": "pairs/s", "cores": thr, "kind": "oracle",
-               "sample": f"first {ns:,} of {N:,} fibers x all {M:,} centroids, float32, the "
-                         f"paper's progressive discard (tests 1-4), OpenMP {thr} threads; "
-                         f"{dt:.1f} s",
+               "sample": f"{'all' if ns == N else 'first'} {ns:,} of {N:,} fibers x all {M:,} "
+                         f"centroids, float32, the paper's progressive discard (tests 1-4), "
+                         f"OpenMP {thr} threads; {dt:.1f} s",
                "fibers_per_s": ns / dt,
                "labels_match_gpu": bool(np.array_equal(l_cpu, ref[0][:ns]))}
         log(f"cpu oracle: {ns} fibers in {dt:.1f}s ({cpu['value']:.3e} pairs/s, {thr} threads)")
@@ -274,7 +345,7 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"config {cfg}: {WORKLOADS[cfg]}", "fibers": N, "centroids": M,
+        "config": {"workload": f"{wl}: {WORKLOADS[wl]}", "fibers": N, "centroids": M,
                    "bundles": at.n_bundles, "mode": head},
         "fibers_per_s": r["fibers_per_s"],
         "prefilter_vs_plain_speedup": speed,

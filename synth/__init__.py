@@ -8,11 +8,12 @@ from .fibers import (  # noqa: F401
     AtlasSpec,
     SubjectSpec,
     Atlas,
-    CONFIGS,
+    WORKLOADS,
     bezier_curves,
     make_atlas,
     make_fibers,
-    config_atlases,
-    config_subjects,
+    workload_atlases,
+    workload_subjects,
+    workload_seed,
     small_case,
 )

@@ -84,32 +84,33 @@ class Atlas:
 _LONG = dict(len_lo=20.0, len_hi=200.0)
 _SHORT = dict(len_lo=20.0, len_hi=80.0)
 
-# The five workloads: small plain case, plain exact path, paper-scale
-# subject (4,145,000 fibers, section 3), large probabilistic-like subject and
-# a batch of uneven subjects against two atlases.
-CONFIGS = {
-    1: dict(
-        name="small-20k-x-800",
+# The five workloads, named by what they are: a small case the oracle runs in
+# full, a plain exact-path case, the paper-scale subject (4,145,000 fibers,
+# section 3), a large probabilistic-like subject and a batch of uneven subjects
+# against two atlases.  Each carries its own seed.
+WORKLOADS = {
+    "small-20k-x-800": dict(
+        seed=12494,
         atlases=[AtlasSpec(40, 20, thr_lo=6.0, thr_hi=10.0, **_LONG)],
         subjects=[SubjectSpec(20_000, 2.0, (0.6,))],
     ),
-    2: dict(
-        name="exact-1M-x-3600",
+    "exact-1M-x-3600": dict(
+        seed=13494,
         atlases=[AtlasSpec(36, 100, thr_lo=6.0, thr_hi=12.0, **_LONG)],
         subjects=[SubjectSpec(1_000_000, 3.0, (0.5,))],
     ),
-    3: dict(
-        name="paper-4145k-x-10k",
+    "paper-4145k-x-10k": dict(
+        seed=14494,
         atlases=[AtlasSpec(100, 100, thr_lo=5.0, thr_hi=8.0, **_SHORT)],
         subjects=[SubjectSpec(4_145_000, 2.0, (0.3,))],
     ),
-    4: dict(
-        name="large-10M-x-20k",
+    "large-10M-x-20k": dict(
+        seed=15494,
         atlases=[AtlasSpec(200, 100, thr_lo=5.0, thr_hi=8.0, **_SHORT)],
         subjects=[SubjectSpec(10_000_000, 2.0, (0.3,))],
     ),
-    5: dict(
-        name="batch-16-subjects-x-2-atlases",
+    "batch-16-subjects-x-2-atlases": dict(
+        seed=16494,
         atlases=[
             AtlasSpec(36, 100, len_lo=80.0, len_hi=200.0, thr_lo=6.0, thr_hi=12.0),
             AtlasSpec(100, 100, thr_lo=5.0, thr_hi=8.0, **_SHORT),
@@ -124,8 +125,8 @@ CONFIGS = {
 }
 
 
-def config_seed(cfg: int) -> int:
-    return 11494 + 1000 * cfg
+def workload_seed(name: str) -> int:
+    return WORKLOADS[name]["seed"]
 
 
 def _rng(*key: int) -> np.random.Generator:
@@ -281,16 +282,16 @@ def make_fibers(atlases: Sequence[Atlas], subject: SubjectSpec, seed: int,
     return out
 
 
-def config_atlases(cfg: int) -> List[Atlas]:
-    seed = config_seed(cfg)
-    return [make_atlas(spec, seed * 10 + i) for i, spec in enumerate(CONFIGS[cfg]["atlases"])]
+def workload_atlases(name: str) -> List[Atlas]:
+    seed = workload_seed(name)
+    return [make_atlas(spec, seed * 10 + i) for i, spec in enumerate(WORKLOADS[name]["atlases"])]
 
 
-def config_subjects(cfg: int) -> List[SubjectSpec]:
-    c = CONFIGS[cfg]
+def workload_subjects(name: str) -> List[SubjectSpec]:
+    c = WORKLOADS[name]
     if c["subjects"] is not None:
         return list(c["subjects"])
-    rng = _rng(config_seed(cfg), 2)
+    rng = _rng(workload_seed(name), 2)
     sizes = rng.integers(c["size_lo"], c["size_hi"] + 1, c["n_subjects"])
     return [SubjectSpec(int(s), c["sigma"], tuple(c["matched"])) for s in sizes]
 

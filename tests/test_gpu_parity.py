@@ -221,32 +221,32 @@ def test_stats_and_determinism(seg):
         assert torch.equal(l2, lab) and torch.equal(d2, dist)
 
 
-@pytest.mark.parametrize("cfg", [2, 3])
-def test_full_size_sampled(seg, cfg):
+@pytest.mark.parametrize("wl", ["exact-1M-x-3600", "paper-4145k-x-10k"])
+def test_full_size_sampled(seg, wl):
     """Full-size workload in the launch configuration the benchmark times;
     the oracle recomputes a fixed sample of fibers one by one."""
     import torch
 
-    at = synth.config_atlases(cfg)[0]
-    subj = synth.config_subjects(cfg)[0]
-    seed = synth.fibers.config_seed(cfg)
-    log(f"full size config {cfg}: generating {subj.n_fibers} fibers")
+    at = synth.workload_atlases(wl)[0]
+    subj = synth.workload_subjects(wl)[0]
+    seed = synth.workload_seed(wl)
+    log(f"full size {wl}: generating {subj.n_fibers} fibers")
     fib = synth.make_fibers([at], subj, seed)
     f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
-    rng = np.random.default_rng(cfg)
+    rng = np.random.default_rng(len(wl))
     idx = np.sort(rng.choice(subj.n_fibers, 3000, replace=False))
     idx = np.concatenate([idx, np.arange(subj.n_fibers - 200, subj.n_fibers)])
     o32 = oracle.segment_f32(fib[idx], at.centroids, at.bundle_id, at.thresholds, mode=oracle.CUT)
     for mode in ALL_MODES:
-        if mode == "dense" and cfg == 3:
-            continue  # about 0.3 s of GPU time; covered at config 2
-        log(f"full size config {cfg} mode {mode}")
+        if mode == "dense" and wl.startswith("paper"):
+            continue  # about 0.3 s of GPU time; covered by the 1M x 3600 case
+        log(f"full size {wl} mode {mode}")
         lab, dist = seg.segment(f, c, b, t, mode=mode)
         torch.cuda.synchronize()
         lab = lab.cpu().numpy()
         dist = dist.cpu().numpy()
         assert_parity(lab[idx], dist[idx], fib[idx], at.centroids, at.bundle_id, at.thresholds,
-                      ctx=f"config {cfg} {mode}", o32=o32)
+                      ctx=f"{wl} {mode}", o32=o32)
         # any-size properties: labels in range, dists finite iff labelled, within threshold
         assert ((lab >= -1) & (lab < at.n_bundles)).all()
         assert (np.isfinite(dist) == (lab >= 0)).all()

@@ -30,13 +30,15 @@ def test_centroid_shapes():
 
 
 def test_config_shapes():
-    for cfg, (m, b) in {1: (800, 40), 2: (3600, 36), 3: (10000, 100), 4: (20000, 200)}.items():
-        spec = synth.CONFIGS[cfg]["atlases"][0]
+    for name, (m, b) in {"small-20k-x-800": (800, 40), "exact-1M-x-3600": (3600, 36),
+                         "paper-4145k-x-10k": (10000, 100),
+                         "large-10M-x-20k": (20000, 200)}.items():
+        spec = synth.WORKLOADS[name]["atlases"][0]
         assert spec.n_centroids == m and spec.n_bundles == b
-    assert synth.config_subjects(3)[0].n_fibers == 4_145_000
-    s5 = synth.config_subjects(5)
+    assert synth.workload_subjects("paper-4145k-x-10k")[0].n_fibers == 4_145_000
+    s5 = synth.workload_subjects("batch-16-subjects-x-2-atlases")
     assert len(s5) == 16 and all(300_000 <= s.n_fibers <= 4_100_000 for s in s5)
-    assert [a.n_centroids for a in synth.CONFIGS[5]["atlases"]] == [3600, 10000]
+    assert [a.n_centroids for a in synth.WORKLOADS["batch-16-subjects-x-2-atlases"]["atlases"]] == [3600, 10000]
 
 
 def test_matched_fraction():
