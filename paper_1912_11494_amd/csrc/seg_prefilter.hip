@@ -507,16 +507,16 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
   constexpr int FPW = GF * 32;
   constexpr int CH = Chunk<KP>::CH;
   constexpr int CCOLS = 32 * CH;  // columns per chunk (<= 256 = one per thread)
-  // A group of 32 fibers x 32 columns adds at most 1024 entries; the queue is
-  // drained before a group whenever that might not fit.
-  constexpr int QCAP = 2048;
+  // The queue takes at most 64 entries per push (one per lane) and is drained
+  // before a push whenever fewer than 64 places are left.
+  constexpr int QCAP = 512;
   static_assert(FPW <= 256, "slot must fit 8 bits");
   static_assert(CCOLS <= 256, "one chunk column per thread");
   static_assert(CH % 2 == 0, "accumulator sets alternate within a chunk");
   __shared__ FT s_feat[3][CH][KS][2][32];
   __shared__ float s_cb[3][CH][32];
-  // (tile, group) pairs with a survivor, processed after the centroid loop
-  constexpr int HCAP = 512;
+  // tiles with a survivor, processed after the centroid loop
+  constexpr int HCAP = 256;
   __shared__ uint32_t s_hits[WAVES][HCAP];
   __shared__ uint32_t s_queue[PAIRS ? 1 : WAVES][PAIRS ? 1 : QCAP];
   __shared__ uint64_t s_keys[PAIRS ? 1 : WAVES][PAIRS ? 1 : FPW];
@@ -607,54 +607,52 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
   issue(0, 0);
   fetch(1, 0, 1);
 
-  // Survivor extraction for one (tile, group): the products are recomputed
-  // (one more MFMA; hits are rare) and every (fiber, centroid) above cb is
-  // pushed.  `b` and `cb` are the tile's fragment and column constant.
+  // Survivor extraction for one tile, after the centroid loop: the products
+  // of every fiber group are recomputed (one more MFMA each; hits are rare)
+  // and every (fiber, centroid) at or above cb is pushed.
   uint32_t qn = 0;
-  auto extract = [&](const FT* b, float cb, int32_t tile, int g) {
-    f32x16 a = Frag<Q>::mfma(afr[g][0], b[0], negh[g]);
-#pragma unroll
-    for (int s = 1; s < KS; ++s) a = Frag<Q>::mfma(afr[g][s], b[s], a);
-    const int32_t col = tile * 32 + (lane & 31);
-    const uint32_t cent = (uint32_t)(col / CPC);
-    if (!PAIRS && qn > (uint32_t)(QCAP - 1024)) {
-      queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
-      qn = 0;
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int slot = g * 32 + out_row(lane, r);
-      const bool p = a[r] >= cb && wbase + slot < n;
-      const uint64_t msk = __ballot(p);
-      if (!msk) continue;
-      if (PAIRS) {
-        if (p) {
-          const unsigned long long kk = atomicAdd(counters, 1ull);
-          if ((int64_t)kk < cap) {
-            pairs[2 * kk] = (int32_t)(wbase + slot);
-            pairs[2 * kk + 1] = (int32_t)cent;
-          }
-        }
-      } else {
-        queue_push(wq, qn, msk, (cent << 8) | (uint32_t)slot);
-      }
-    }
-  };
-  auto extract_global = [&](int32_t tile, int g) {
+  auto extract_tile = [&](int32_t tile) {
     const int32_t col = tile * 32 + (lane & 31);
     FT b[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
       b[s] = *(const FT*)(cfeat + (int64_t)col * (KP * EB) + (s * 16 + 8 * half) * EB);
     const float cb = cbias[col];
+    const uint32_t cent = (uint32_t)(col / CPC);
 #pragma unroll
-    for (int gg = 0; gg < GF; ++gg)
-      if (gg == g) extract(b, cb, tile, gg);
+    for (int g = 0; g < GF; ++g) {
+      f32x16 a = Frag<Q>::mfma(afr[g][0], b[0], negh[g]);
+#pragma unroll
+      for (int s = 1; s < KS; ++s) a = Frag<Q>::mfma(afr[g][s], b[s], a);
+      if (!wave_any(max16(a) >= cb)) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int slot = g * 32 + out_row(lane, r);
+        const bool p = a[r] >= cb && wbase + slot < n;
+        const uint64_t msk = __ballot(p);
+        if (!msk) continue;
+        if (PAIRS) {
+          if (p) {
+            const unsigned long long kk = atomicAdd(counters, 1ull);
+            if ((int64_t)kk < cap) {
+              pairs[2 * kk] = (int32_t)(wbase + slot);
+              pairs[2 * kk + 1] = (int32_t)cent;
+            }
+          }
+        } else {
+          if (qn > (uint32_t)(QCAP - 64)) {
+            queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
+            qn = 0;
+          }
+          queue_push(wq, qn, msk, (cent << 8) | (uint32_t)slot);
+        }
+      }
+    }
   };
 
-  // The hot loop only records hits (wave-uniform list in LDS); extraction
-  // happens after the loop so that the waves of a block stay in step between
-  // barriers.  A full list falls back to extracting at once.
+  // The hot loop only records which tiles have a lane at or above cb (a
+  // wave-uniform list in LDS, in increasing tile order).  If the list fills
+  // up, the tiles after the last recorded one are scanned again afterwards.
   uint32_t nh = 0;
   uint32_t* hl = s_hits[wave];
   int buf = 0;
@@ -672,19 +670,12 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
       else
         fetch(u & 1, fbuf, u + 2 - CH);
       const int cs = u & 1;
-      const float cb = cbc[cs];
+      float mx = max16(acc[cs][0]);
 #pragma unroll
-      for (int g = 0; g < GF; ++g) {
-        const float mx = max16(acc[cs][g]);
-        if (wave_any(mx >= cb)) {
-          const int32_t tile = k * CH + u;
-          if (nh < (uint32_t)HCAP) {
-            if (lane == 0) hl[nh] = ((uint32_t)tile << 3) | (uint32_t)g;
-            ++nh;
-          } else {
-            extract_global(tile, g);
-          }
-        }
+      for (int g = 1; g < GF; ++g) mx = __builtin_fmaxf(mx, max16(acc[cs][g]));
+      if (wave_any(mx >= cbc[cs])) {
+        if (nh < (uint32_t)HCAP && lane == 0) hl[nh] = (uint32_t)(k * CH + u);
+        ++nh;
       }
     }
     // chunk k+2 goes into the buffer of chunk k-1 (nobody reads it any more)
@@ -692,9 +683,18 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
     __syncthreads();
     buf = nbuf;
   }
-  for (uint32_t i = 0; i < nh; ++i) {
-    const uint32_t e = hl[i];
-    extract_global((int32_t)(e >> 3), (int)(e & 7u));
+  const int32_t ntiles = nchunks * CH;
+  const uint32_t nrec = nh < (uint32_t)HCAP ? nh : (uint32_t)HCAP;
+  int32_t scan = nh > (uint32_t)HCAP ? (int32_t)hl[HCAP - 1] + 1 : ntiles;
+  for (uint32_t i = 0;; ++i) {
+    int32_t tile;
+    if (i < nrec)
+      tile = (int32_t)hl[i];
+    else if (scan < ntiles)
+      tile = scan++;
+    else
+      break;
+    extract_tile(tile);
   }
   if (PAIRS) return;
   queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);

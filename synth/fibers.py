@@ -269,8 +269,14 @@ def make_fibers(atlases: Sequence[Atlas], subject: SubjectSpec, seed: int,
     if workers > 1 and len(jobs) > 1:
         import multiprocessing as mp
 
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+        # close + join (not terminate): the workers end on their own, with no
+        # signal, which matters when a profiler has hooked the process
+        pool = mp.get_context("fork").Pool(min(workers, len(jobs)))
+        try:
             chunks = pool.map(_chunk_job, jobs, chunksize=1)
+        finally:
+            pool.close()
+            pool.join()
     else:
         chunks = map(_chunk_job, jobs)
     for c, chunk in zip(range(c0, c1), chunks):

@@ -153,6 +153,20 @@ def test_empty_and_single(seg, mode):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("mode", PREFILTER_MODES)
+def test_every_tile_hits(seg, mode):
+    """Thresholds far above every distance: every pair survives the first cut,
+    so each wave has a hit in every centroid tile (9,000 centroids: 282 tiles,
+    more than a wave records during the centroid loop) and the survivor queue
+    fills and drains many times.  The result is the nearest centroid."""
+    fib, at = synth.small_case(300, 90, 100, seed=21)
+    thr = np.full(at.n_bundles, 1000.0, np.float32)
+    log(f"every tile hits mode={mode} m={at.n_centroids}")
+    lab, dist = run(seg, fib, at.centroids, at.bundle_id, thr, mode)
+    assert_parity(lab, dist, fib, at.centroids, at.bundle_id, thr, ctx=f"all-hit {mode}")
+    assert (lab >= 0).all()
+
+
 def test_validation_errors(seg):
     import torch
 
