@@ -82,7 +82,16 @@ typedef struct seg_options {
   int32_t validate;      /* 1: check inputs on the device and synchronise the
                             stream to report SEG_EBUNDLE / SEG_ENONFINITE */
   int32_t tile;          /* 0: library choice (autotuned cache if present);
-                            k > 0: kernel configuration k of the mode */
+                            k > 0: kernel configuration k of the mode.
+                            DENSE 1-2, PLAIN 1, 2, 4; BF16 / FP16 / FP8:
+                            1-7 stream every centroid tile through the
+                            matrix cores (feature width 16, 32 or 48; 1, 2
+                            or 4 fiber groups per wave), 8 sorts fibers and
+                            centroids by the cell of their center point and
+                            skips (fiber group, centroid tile) pairs whose
+                            feature boxes are too far apart to match (the
+                            library choice for these modes);
+                            BF16_ORIENTED 1-2 */
   int32_t collect_stats; /* 1: count survivors per stage (read with
                             seg_query_stats; adds atomics, not for timing) */
   void* profile_events;  /* optional host pointer to two hipEvent_t: the
@@ -101,6 +110,9 @@ typedef struct seg_stats {
   int64_t accepted;        /* pairs with D <= T2 */
   int64_t labelled;        /* fibers with a label */
   int64_t drains;          /* survivor-queue drains (wave level) */
+  int64_t bound_pairs;     /* pairs the first cut evaluated one by one: N * M,
+                              except for the tile-culled prefilter, which
+                              skips whole (32 fibers x 32 columns) tiles */
 } seg_stats;
 
 /* Default options (mode SEG_PLAIN, no validation, library tiles, no stats,

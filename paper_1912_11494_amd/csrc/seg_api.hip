@@ -135,7 +135,7 @@ std::vector<int> mode_tiles(int mode) {
     case SEG_DENSE: return {1, 2};
     case SEG_PLAIN: return {1, 2, 4};
     case SEG_PREFILTER_BF16_ORIENTED: return {1, 2};
-    default: return {1, 3, 4, 6};  // symmetric prefilters (K, fiber groups)
+    default: return {1, 3, 4, 6, 8};  // symmetric prefilters (K, fiber groups; 8: culled)
   }
 }
 
@@ -146,6 +146,7 @@ thread_local int64_t t_stats_pairs = 0;
 thread_local int64_t t_stats_n = 0;
 thread_local int32_t* t_stats_labels = nullptr;
 thread_local int t_stats_mode = 0;
+thread_local bool t_stats_culled = false;
 
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
@@ -243,6 +244,8 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
     t_stats_n = n;
     t_stats_labels = labels;
     t_stats_mode = o.mode;
+    t_stats_culled = o.mode >= SEG_PREFILTER_BF16 && o.mode <= SEG_PREFILTER_FP8 &&
+                     (tile == 8 || (tile == 0 && n < ((int64_t)1 << 31)));
   }
   return 0;
 }
@@ -566,6 +569,7 @@ int seg_query_stats(seg_stats* out) {
   out->test3_pass = (int64_t)c[2];
   out->accepted = (int64_t)c[3];
   out->drains = (int64_t)c[4];
+  out->bound_pairs = t_stats_culled ? (int64_t)c[5] * 1024 : t_stats_pairs;
   out->labelled = -1;
   return SEG_OK;
 }

@@ -24,7 +24,24 @@ struct PrefilterBuf {
   float* fib_h = nullptr;     // per-fiber bound terms
   size_t fib_h_bytes = 0;
   unsigned int* emax = nullptr;  // device max of the fiber quantisation error
+  // sorted, tile-culled form (seg_cull.hip)
+  void* tbox = nullptr;   // feature boxes and radii of centroid tiles
+  size_t tbox_bytes = 0;
+  void* keys = nullptr;   // sort keys, two buffers
+  size_t keys_bytes = 0;
+  void* vals = nullptr;   // sort values, two buffers (the fiber permutation)
+  size_t vals_bytes = 0;
+  void* hist = nullptr;   // digit counts per block + digit offsets
+  size_t hist_bytes = 0;
+  void* cperm = nullptr;  // sorted column -> centroid
+  size_t cperm_bytes = 0;
+  void* fkeys = nullptr;  // per-fiber argmin keys + the survivor-list counter
+  size_t fkeys_bytes = 0;
+  void* list = nullptr;   // survivor pairs for the exact stage
+  size_t list_bytes = 0;
 };
+
+struct PfParams;
 
 // Library-owned batch scratch: the device job list and the last captured HIP
 // graph with the launch shape it was captured for.
@@ -73,6 +90,15 @@ int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
                   float* dists, unsigned long long* counters, PrefilterBuf& pb, hipEvent_t* ev,
                   hipStream_t s);
+// Frame set-up shared by the prefilter forms: reset the parameters and take
+// the bounding box of the atlas points (seg_prefilter.hip).
+int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
+
+// Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
+int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
+             const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
+             PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s);
+
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,
                     unsigned long long* count, PrefilterBuf& pb, hipStream_t s);

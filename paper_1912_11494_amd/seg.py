@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("pairs", "filter_pass", "test2_pass", "test3_pass", "accepted", "labelled",
-                 "drains")]
+                 "drains", "bound_pairs")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

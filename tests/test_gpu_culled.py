@@ -1,0 +1,157 @@
+"""GPU parity of the sorted, tile-culled prefilter (kernel configuration 8 of
+the symmetric prefilter modes) through the C ABI.
+
+Labels and distances must equal the float32 oracle bit for bit, and the
+number of pairs the exact stage accepts must equal the number of pairs the
+oracle accepts: a tile skipped by the box test may hold no accepted pair.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import assert_parity, run, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+CULL = 8
+MODES = ["bf16", "fp16", "fp8"]
+
+
+@pytest.fixture(scope="module")
+def seg():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need the GPU"
+    import paper_1912_11494_amd as P
+
+    P.lib()
+    return P
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check(seg, fib, cen, bid, thr, mode, ctx, check_f64=True):
+    import torch
+
+    f, c, b, t = to_gpu(fib, cen, bid, thr)
+    lab, dist = seg.segment(f, c, b, t, mode=mode, tile=CULL, stats=True)
+    torch.cuda.synchronize()
+    st = seg.query_stats()
+    lab, dist = lab.cpu().numpy(), dist.cpu().numpy()
+    assert_parity(lab, dist, fib, cen, bid, thr, ctx=ctx, check_f64=check_f64)
+    acc = oracle.accepted_pairs_f32(fib, cen, bid, thr)
+    assert st["accepted"] == len(acc), f"{ctx}: accepted {st['accepted']} vs oracle {len(acc)}"
+    assert st["filter_pass"] >= st["accepted"]
+    # whole tiles of 32 (padded) fibers x 32 (padded) columns are evaluated
+    pad = lambda k: (k + 31) // 32 * 32
+    assert st["bound_pairs"] <= pad(len(fib)) * pad(len(cen))
+    return lab, dist, st
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,nb,per,seed", [(3001, 7, 47, 1), (1000, 40, 20, 2), (257, 3, 5, 3),
+                                           (6000, 12, 30, 4), (20000, 40, 20, 31)])
+def test_culled_ragged(seg, mode, n, nb, per, seed):
+    fib, at = synth.small_case(n, nb, per, seed=seed)
+    log(f"culled mode={mode} n={n} m={nb * per} seed={seed}")
+    lab, _, st = _check(seg, fib, at.centroids, at.bundle_id, at.thresholds, mode,
+                        f"culled {mode} n={n}")
+    assert (lab >= 0).mean() > 0.3
+    log(f"  bound pairs {st['bound_pairs']} of {st['pairs']}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_skips_tiles(seg, mode):
+    """On a spatially spread workload most (group, tile) pairs are skipped."""
+    fib, at = synth.small_case(30000, 100, 100, seed=32, len_lo=20.0, len_hi=80.0,
+                               thr_lo=5.0, thr_hi=8.0, matched=0.3)
+    log(f"culled skip mode={mode}")
+    _, _, st = _check(seg, fib, at.centroids, at.bundle_id, at.thresholds, mode,
+                      f"culled skip {mode}", check_f64=False)
+    frac = st["bound_pairs"] / st["pairs"]
+    log(f"  bound pairs {frac:.3f} of all pairs")
+    assert frac < 0.5
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_adversarial(seg, mode):
+    from test_gpu_parity import _adversarial
+
+    fib, cen, bid, thr = _adversarial()
+    log(f"culled adversarial mode={mode}")
+    lab, dist, _ = _check(seg, fib, cen, bid, thr, mode, f"culled adversarial {mode}",
+                          check_f64=False)
+    assert dist[-1] == 0 and dist[-2] == 0
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_special_thresholds(seg, mode):
+    fib, at = synth.small_case(700, 5, 9, seed=12)
+    thr = np.array([np.inf, -1.0, 7.0, -0.0, np.inf], np.float32)
+    log(f"culled special thresholds mode={mode}")
+    lab, _, _ = _check(seg, fib, at.centroids, at.bundle_id, thr, mode,
+                       f"culled special {mode}", check_f64=False)
+    assert not np.isin(lab, [1]).any()
+    lab, dist = run(seg, fib, at.centroids, at.bundle_id, np.full(5, -3.0, np.float32), mode,
+                    tile=CULL)
+    assert (lab == -1).all() and np.isinf(dist).all()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_every_tile_hits(seg, mode):
+    """Thresholds far above every distance: nothing can be skipped, two rounds
+    of 256 tiles (9,000 centroids), many queue drains."""
+    fib, at = synth.small_case(300, 90, 100, seed=21)
+    thr = np.full(at.n_bundles, 1000.0, np.float32)
+    log(f"culled all-hit mode={mode}")
+    lab, _, st = _check(seg, fib, at.centroids, at.bundle_id, thr, mode, f"culled all-hit {mode}")
+    assert (lab >= 0).all()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_overflow_list(seg, mode):
+    """Wide thresholds: each wave of 64 fibers has more survivors than its own
+    part of the survivor list holds, so the shared overflow list is used."""
+    fib, at = synth.small_case(4000, 20, 100, seed=22, len_lo=20.0, len_hi=60.0)
+    thr = (at.thresholds * 4.0).astype(np.float32)
+    log(f"culled overflow mode={mode}")
+    _, _, st = _check(seg, fib, at.centroids, at.bundle_id, thr, mode, f"culled overflow {mode}",
+                      check_f64=False)
+    per_wave = st["filter_pass"] / ((len(fib) + 63) // 64)
+    log(f"  survivors per wave {per_wave:.0f}")
+    assert per_wave > 512
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_empty_and_single(seg, mode):
+    import torch
+
+    fib, at = synth.small_case(130, 3, 4, seed=13)
+    cen, bid, thr = at.centroids, at.bundle_id, at.thresholds
+    log(f"culled empty/single mode={mode}")
+    lab, dist = run(seg, fib, cen[:0], bid[:0], thr, mode, tile=CULL)
+    assert (lab == -1).all() and np.isinf(dist).all()
+    f, c, b, t = to_gpu(fib[:0], cen, bid, thr)
+    l0, _ = seg.segment(f, c, b, t, mode=mode, tile=CULL)
+    assert l0.numel() == 0
+    lab, dist = run(seg, fib[:1], cen[:1], bid[:1] * 0, thr[:1], mode, tile=CULL)
+    assert_parity(lab, dist, fib[:1], cen[:1], bid[:1] * 0, thr[:1], ctx="1x1", check_f64=False)
+    torch.cuda.synchronize()
+
+
+def test_culled_matches_streaming(seg):
+    """Same labels and distances as the streaming kernels, repeated calls."""
+    fib, at = synth.small_case(9000, 30, 40, seed=33, len_lo=20.0, len_hi=80.0)
+    outs = []
+    for mode in MODES:
+        for tile in (1, CULL, CULL):
+            log(f"culled vs streaming mode={mode} tile={tile}")
+            outs.append(run(seg, fib, at.centroids, at.bundle_id, at.thresholds, mode, tile=tile))
+    for lab, dist in outs[1:]:
+        assert np.array_equal(lab, outs[0][0]) and np.array_equal(dist, outs[0][1])
