@@ -2,18 +2,19 @@
 """Benchmark of the segmentation hot path on one MI355X.
 
 One step = one pass of the whole path over one subject resident in HBM:
-atlas preparation, the first cut (center test or MFMA prefilter), the exact
-float32 stage on survivors and the per-fiber argmin / label write.  The
-workload is the paper-scale subject: 4,145,000 fibers against 10,000
-centroids (100 bundles x 100), 21 points of float32 each, synthetic.
+atlas preparation, the first cut (center test or MFMA prefilter, with its
+feature preparation, sort and tile culling), the exact float32 stage on
+survivors and the per-fiber argmin / label write.  The workload is the
+paper-scale subject: 4,145,000 fibers against 10,000 centroids (100 bundles x
+100), 21 points of float32 each, synthetic.
 
     python bench.py [--steps K] [--warmup W] [--mode bf16|plain|dense|...]
 
 Prints one JSON line.  `value` is pairs/s of the headline mode (N*M per
-step); every other compared mode is reported under "modes".  The dominant
-kernel of the headline mode is timed live with HIP events recorded by the
-library right around its launch (seg_options.profile_events), on the stream
-the kernel runs on.
+step); every other compared mode (``mode`` or ``mode:tile``) is reported
+under "modes".  The dominant kernel of each mode is timed live with HIP
+events recorded by the library right around its launch
+(seg_options.profile_events), on the stream the kernel runs on.
 """
 from __future__ import annotations
 
@@ -41,7 +42,9 @@ WORKLOADS = {
     "large-10M-x-20k": "10,000,000 fibers x 20,000 centroids (200 bundles x 100), 21 pts fp32",
 }
 # kernels whose HBM traffic is summarised: counter-file kernel-name prefix -> key
-TRAFFIC_KERNELS = [("seg::prefilter_kernel<0,", "prefilter_kernel:bf16"),
+TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf16"),
+                   ("seg::(anonymousnamespace)::cull_kernel<1,", "cull_kernel:fp16"),
+                   ("seg::prefilter_kernel<0,", "prefilter_kernel:bf16"),
                    ("seg::prefilter_kernel<1,", "prefilter_kernel:fp16"),
                    ("seg::prefilter_kernel<2,", "prefilter_kernel:fp8"),
                    ("seg::plain_kernel<", "plain_kernel"),
@@ -186,13 +189,14 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
 
 def alg_flops(mode, st, n, m, kfeat=None):
     """Algorithmic FLOPs of the dominant kernel per launch (8 FLOP per point
-    distance: 3 sub, 3 mul, 2 add)."""
+    distance: 3 sub, 3 mul, 2 add; 2 per multiply-add of the matrix product).
+    The tile-culled prefilter evaluates its bound only on `bound_pairs`."""
     if mode == "dense":
         return 328.0 * n * m  # 41 distinct point distances per pair
     exact = 32.0 * st["filter_pass"] + 64.0 * st["test2_pass"] + 224.0 * st["test3_pass"]
     if mode == "plain":
         return 8.0 * n * m + exact
-    return 2.0 * kfeat * n * m  # prefilter product (the exact stage is reported apart)
+    return 2.0 * kfeat * st["bound_pairs"]  # the exact stage is a kernel of its own
 
 
 def main():
@@ -202,7 +206,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper-4145k-x-10k", choices=list(WORKLOADS))
     ap.add_argument("--mode", default=None, help="headline mode (default: fastest built)")
-    ap.add_argument("--compare", default="plain,dense,bf16,fp16,bf16_oriented,fp8")
+    ap.add_argument("--compare", default="plain,dense,bf16,fp16,fp8,bf16_oriented,fp16:1,bf16:1",
+                    help="modes to time, `mode` (library tile) or `mode:tile`")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="fibers of the workload the CPU oracle is timed on (0: all)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -257,24 +262,27 @@ def main():
 
     modes = {}
     outs = {}
-    for mode in [m for m in args.compare.split(",") if m]:
+    for spec in [m for m in args.compare.split(",") if m]:
+        mode, _, tile = spec.partition(":")
+        tile = int(tile or 0)
         try:
-            P.segment(f, c, b, t, mode=mode)
+            P.segment(f, c, b, t, mode=mode, tile=tile)
         except P.SegError as e:
-            log(f"mode {mode}: not available ({e})")
+            log(f"mode {spec}: not available ({e})")
             continue
         torch.cuda.synchronize()
-        r, out = time_mode(P, hip, f, c, b, t, mode, args.steps, args.warmup)
-        P.segment(f, c, b, t, mode=mode, stats=True)
+        r, out = time_mode(P, hip, f, c, b, t, mode, args.steps, args.warmup, tile)
+        P.segment(f, c, b, t, mode=mode, tile=tile, stats=True)
         st = P.query_stats()
+        r["tile"] = tile
         r["pairs_per_s"] = N * M / (r["ms_per_step"] * 1e-3)
         r["fibers_per_s"] = N / (r["ms_per_step"] * 1e-3)
         r["survivors_per_fiber"] = st["filter_pass"] / N if mode != "dense" else None
         r["accepted_pairs"] = st["accepted"] if mode != "dense" else None
         r["stats"] = st
-        modes[mode] = r
-        outs[mode] = (out[0].cpu().numpy(), out[1].cpu().numpy())
-        log(f"mode {mode}: {r['ms_per_step']:.3f} ms/step, kernel {r['kernel_ms']:.3f} ms, "
+        modes[spec] = r
+        outs[spec] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+        log(f"mode {spec}: {r['ms_per_step']:.3f} ms/step, kernel {r['kernel_ms']:.3f} ms, "
             f"{r['pairs_per_s']:.3e} pairs/s")
 
     if not modes:
@@ -288,28 +296,42 @@ def main():
         prod = [m for m in ("bf16", "fp16", "plain") if m in modes]
         head = min(prod, key=lambda m: modes[m]["ms_per_step"])
     r = modes[head]
-    kfeat = r["stats"].get("kfeat") if isinstance(r.get("stats"), dict) else None
+
+    def mfma_roofline(spec):
+        """The prefilter product of mode `spec`: algorithmic width 15 features
+        (symmetric map, 4 point groups) or 2 orders x 63 coordinates (oriented)."""
+        mode = spec.split(":")[0]
+        x = modes[spec]
+        peak = PEAK_FP8 if mode == "fp8" else PEAK_BF16
+        kf = {"bf16_oriented": 126}.get(mode, 15)
+        ach = alg_flops(mode, x["stats"], N, M, kf) / (x["kernel_ms"] * 1e-3) / 1e12
+        culled = x["stats"]["bound_pairs"] < x["stats"]["pairs"]
+        kname = "cull_kernel" if culled else "prefilter_kernel"
+        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": traffic_for(f"{kname}:{mode}"), "kernel": kname,
+                "kernel_ms": x["kernel_ms"],
+                "bound_pairs_frac": x["stats"]["bound_pairs"] / x["stats"]["pairs"]}
+
     if head in ("dense", "plain"):
-        bound, peak, kname = "alu", PEAK_FP32, f"{head}_kernel"
         ach = alg_flops(head, r["stats"], N, M) / (r["kernel_ms"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                    "frac": ach / PEAK_FP32, "traffic": traffic_for(f"{head}_kernel"),
+                    "kernel": f"{head}_kernel", "kernel_ms": r["kernel_ms"]}
         dtype = "f32"
     else:
-        bound, kname = "mfma", "prefilter_kernel"
-        peak = PEAK_FP8 if head == "fp8" else PEAK_BF16
-        # algorithmic width of the product: 15 features (symmetric map, 4
-        # point groups) or 2 orders x 63 coordinates (oriented map)
-        kf = {"bf16_oriented": 126}.get(head, 15)
-        ach = alg_flops(head, r["stats"], N, M, kf) / (r["kernel_ms"] * 1e-3) / 1e12
-        dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head, "bf16+f32")
-    tkey = kname if head in ("dense", "plain") else f"{kname}:{head}"
-    roofline = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": traffic_for(tkey), "kernel": kname,
-                "kernel_ms": r["kernel_ms"]}
+        roofline = mfma_roofline(head)
+        dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head.split(":")[0], "bf16+f32")
+    # the compute-bound kernels of the other forms, for reference
+    for spec in (f"{head}:1", "fp16:1", "bf16:1"):
+        if spec in modes and spec != head:
+            roofline["streaming_prefilter"] = dict(mfma_roofline(spec), mode=spec)
+            break
     if "dense" in modes:
         dm = modes["dense"]
         a_d = alg_flops("dense", None, N, M) / (dm["kernel_ms"] * 1e-3) / 1e12
         roofline["exact_stage_dense"] = {"achieved": a_d, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                                         "frac": a_d / PEAK_FP32, "kernel_ms": dm["kernel_ms"]}
+                                         "frac": a_d / PEAK_FP32, "kernel_ms": dm["kernel_ms"],
+                                         "traffic": traffic_for("dense_kernel")}
 
     cpu = None
     if not args.no_cpu:

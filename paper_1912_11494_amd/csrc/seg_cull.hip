@@ -929,16 +929,17 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
                     n, cprep, fkeys, list, list_n, ovf, ovf_count, ovf_cap};
   const unsigned blocks = (unsigned)(n_pad / 256);
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return -1;
-  if (counters) {
+  if (counters)
     cull_kernel<Q, true><<<blocks, 256, 0, s>>>(job, counters);
+  else
+    cull_kernel<Q, false><<<blocks, 256, 0, s>>>(job, counters);
+  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
+  if (counters)
     exact_list_kernel<true, CULL_QCAP><<<blocks, 256, 0, s>>>(
         list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters);
-  } else {
-    cull_kernel<Q, false><<<blocks, 256, 0, s>>>(job, counters);
+  else
     exact_list_kernel<false, CULL_QCAP><<<blocks, 256, 0, s>>>(
         list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters);
-  }
-  if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
   if (counters)
     rescue_kernel<true><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys,
                                                counters);
