@@ -50,8 +50,10 @@ TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf
                    ("seg::plain_kernel<", "plain_kernel"),
                    ("seg::dense_kernel<1>", "dense_kernel")]
 KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
+                  "paper_1912_11494_amd/csrc/seg_pf.hpp",
                   "paper_1912_11494_amd/csrc/seg_kernels.hip",
-                  "paper_1912_11494_amd/csrc/seg_prefilter.hip"]
+                  "paper_1912_11494_amd/csrc/seg_prefilter.hip",
+                  "paper_1912_11494_amd/csrc/seg_cull.hip"]
 
 
 def log(msg):
