@@ -24,6 +24,10 @@ LIB = os.path.join(HERE, "libseg_oracle.so")
 BRUTE = 0
 CUT = 1
 
+# metric variants (flags of segment_ext_f32)
+TN = 1    # length normalisation (Eq. 3)
+DIR = 2   # direction inference (section 2.4)
+
 # -ffp-contract=off: the float32 expression must be evaluated exactly as
 # written (one explicit fmaf per step, nothing fused by the compiler).
 CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -67,6 +71,13 @@ class Oracle:
         L.oracle_accepted_pairs_f32.argtypes = [P, i64, P, i64, P, P, i32, P, i64]
         L.oracle_accepted_pairs_f32.restype = ctypes.c_int64
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_segment_ext_f32.argtypes = [P, i64, P, i64, P, P, i32, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, P, P, P]
+        L.oracle_segment_ext_f32.restype = ctypes.c_int
+        L.oracle_arc_length_f32.argtypes = [P]
+        L.oracle_arc_length_f32.restype = ctypes.c_float
+        L.oracle_tn_f32.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.oracle_tn_f32.restype = ctypes.c_float
         self.L = L
         self.path = path
 
@@ -95,6 +106,29 @@ class Oracle:
         if rc:
             raise ValueError(f"oracle_segment_f32 failed ({rc})")
         return labels, dists, best
+
+    def segment_ext_f32(self, fibers, centroids, bid, thr, flags: int, mode: int = CUT,
+                        threads: int = 0):
+        """float32 decision with metric variants (TN | DIR): (labels, dists, best)."""
+        keep, pf, pc, pb, pt = self._prep(fibers, centroids, bid, thr)
+        f, c, b, t = keep
+        n = f.shape[0]
+        labels = np.empty(n, np.int32)
+        dists = np.empty(n, np.float32)
+        best = np.empty(n, np.int32)
+        rc = self.L.oracle_segment_ext_f32(pf, n, pc, c.shape[0], pb, pt, t.shape[0], mode, flags,
+                                           threads, labels.ctypes.data, dists.ctypes.data,
+                                           best.ctypes.data)
+        if rc:
+            raise ValueError(f"oracle_segment_ext_f32 failed ({rc})")
+        return labels, dists, best
+
+    def arc_length_f32(self, p) -> float:
+        p, pp = _c(p, np.float32)
+        return float(self.L.oracle_arc_length_f32(pp))
+
+    def tn_f32(self, ls: float, lc: float) -> float:
+        return float(self.L.oracle_tn_f32(ls, lc))
 
     def segment_f64(self, fibers, centroids, bid, thr, threads: int = 0):
         """float64 companion: (labels int32, dists float64, best centroid int32)."""
@@ -173,3 +207,7 @@ def pair_f64(a, b):
 
 def accepted_pairs_f32(*a, **k):
     return get().accepted_pairs_f32(*a, **k)
+
+
+def segment_ext_f32(*a, **k):
+    return get().segment_ext_f32(*a, **k)

@@ -41,6 +41,22 @@
  *                 exceeding point and a pair dies when both orders died.
  *                 The four intermediate points are 4, 8, 12 and 16 (the paper
  *                 does not name them; any choice gives the same result).
+ * Metric variants (oracle_segment_ext_f32), flags:
+ *   VAR_TN   length normalisation (section 2.3, Eq. 3): for an accepted pair the
+ *            complete metric is  d_ME + TN,  TN = (|l_S - l_C| / max(l_S, l_C) + 1)^2 - 1
+ *            with l the arc length of the 21-point polyline; the pair is kept
+ *            when D <= T2 and d_ME + TN <= T, and the fiber takes the bundle of
+ *            the smallest complete metric (readings: the metric is compared
+ *            with the threshold, TN = 0 when both lengths are 0, the reported
+ *            distance is the complete metric);
+ *   VAR_DIR  direction inference (section 2.4, "Inference of fiber
+ *            direction"): the order with the smaller largest end-point
+ *            distance (direct on ties) is the fiber's direction and D is the
+ *            largest point distance of that order only.
+ *   float32 expressions: segment length sqrtf(fmaf(dz, dz, fmaf(dy, dy,
+ *   dx * dx))) of p[i+1] - p[i], summed in point order; r = |lS - lC| / max
+ *   (rounded once), u = r + 1, TN = u * u - 1 (each rounded); the complete
+ *   metric sqrtf(D) + TN (rounded once).
  * Precisions:
  *   *_f32  the float32 decision above (labels must match it bit for bit);
  *   *_f64  the same definition in double precision with exact differences,
@@ -59,6 +75,7 @@
 #define CENTER 10
 
 enum { ORACLE_BRUTE = 0, ORACLE_CUT = 1 };
+enum { VAR_TN = 1, VAR_DIR = 2 };
 
 /* ---------------------------------------------------------------- float32 */
 
@@ -221,6 +238,137 @@ int64_t oracle_accepted_pairs_f32(const float* fibers, int64_t n, const float* c
     }
   }
   return cnt;
+}
+
+/* ---------------------------------------------------------------- variants */
+
+/* Arc length of a 21-point polyline (float32, segments summed in order). */
+float oracle_arc_length_f32(const float* p) {
+  float l = 0.0f;
+  for (int i = 0; i + 1 < NP; ++i) {
+    float dx = p[3 * (i + 1)] - p[3 * i];
+    float dy = p[3 * (i + 1) + 1] - p[3 * i + 1];
+    float dz = p[3 * (i + 1) + 2] - p[3 * i + 2];
+    l = l + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
+  return l;
+}
+
+/* Length term of Eq. 3. */
+float oracle_tn_f32(float ls, float lc) {
+  float mx = ls > lc ? ls : lc;
+  if (!(mx > 0.0f)) return 0.0f;
+  float r = fabsf(ls - lc) / mx;
+  float u = r + 1.0f;
+  float uu = u * u;
+  return uu - 1.0f;
+}
+
+/* Direction inference, brute form: the order with the smaller largest
+   end-point distance, then every point of that order. */
+static int eval_dir_brute_f32(const float* a, const float* b, float t2, float* D) {
+  float ed = d2_f32(a, b), ed2 = d2_f32(a + 3 * (NP - 1), b + 3 * (NP - 1));
+  float ei = d2_f32(a, b + 3 * (NP - 1)), ei2 = d2_f32(a + 3 * (NP - 1), b);
+  ed = ed2 > ed ? ed2 : ed;
+  ei = ei2 > ei ? ei2 : ei;
+  int direct = ed <= ei;
+  float mx = 0.0f;
+  for (int i = 0; i < NP; ++i) {
+    float x = d2_f32(a + 3 * i, b + 3 * (direct ? i : NP - 1 - i));
+    mx = x > mx ? x : mx;
+  }
+  if (mx <= t2) {
+    *D = mx;
+    return 1;
+  }
+  return 0;
+}
+
+/* Direction inference as the paper runs it: center, end points (which fix
+   the direction), then the four intermediate points and the rest in that
+   direction only, leaving at the first point above the threshold. */
+static int eval_dir_cut_f32(const float* a, const float* b, float t2, float* D) {
+  static const int four[4] = {4, 8, 12, 16};
+  float c = d2_f32(a + 3 * CENTER, b + 3 * CENTER);
+  if (c > t2) return 0;
+  float x0 = d2_f32(a, b), x1 = d2_f32(a + 3 * (NP - 1), b + 3 * (NP - 1));
+  float y0 = d2_f32(a, b + 3 * (NP - 1)), y1 = d2_f32(a + 3 * (NP - 1), b);
+  float ed = x1 > x0 ? x1 : x0, ei = y1 > y0 ? y1 : y0;
+  int direct = ed <= ei;
+  float mx = direct ? ed : ei;
+  if (mx > t2) return 0;
+  mx = c > mx ? c : mx;
+  for (int k = 0; k < 4; ++k) {
+    int i = four[k];
+    float x = d2_f32(a + 3 * i, b + 3 * (direct ? i : NP - 1 - i));
+    if (x > t2) return 0;
+    mx = x > mx ? x : mx;
+  }
+  for (int i = 1; i < NP - 1; ++i) {
+    if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16) continue;
+    float x = d2_f32(a + 3 * i, b + 3 * (direct ? i : NP - 1 - i));
+    if (x > t2) return 0;
+    mx = x > mx ? x : mx;
+  }
+  *D = mx;
+  return 1;
+}
+
+/*
+ * The float32 decision with metric variants (flags: VAR_TN | VAR_DIR).
+ * Outputs as oracle_segment_f32; dists holds the complete metric with
+ * VAR_TN, sqrtf(D) otherwise.  flags = 0 gives oracle_segment_f32's result.
+ */
+int oracle_segment_ext_f32(const float* fibers, int64_t n, const float* cen, int64_t m,
+                           const int32_t* bid, const float* thr, int32_t nb, int mode, int flags,
+                           int nthreads, int32_t* labels, float* dists, int32_t* best) {
+  int rc = check_args(n, m, bid, nb);
+  if (rc) return rc;
+  float* t2 = (float*)malloc(sizeof(float) * (size_t)(nb > 0 ? nb : 1));
+  float* lc = (float*)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1));
+  for (int32_t b = 0; b < nb; ++b) t2[b] = thr2_f32(thr[b]);
+  for (int64_t c = 0; c < m; ++c) lc[c] = oracle_arc_length_f32(cen + (size_t)c * 3 * NP);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t f = 0; f < n; ++f) {
+    const float* a = fibers + (size_t)f * 3 * NP;
+    const float ls = oracle_arc_length_f32(a);
+    float bestv = 0.0f;
+    int64_t bestc = -1;
+    for (int64_t c = 0; c < m; ++c) {
+      float D;
+      const float* b = cen + (size_t)c * 3 * NP;
+      float tt = t2[bid[c]];
+      int ok;
+      if (flags & VAR_DIR)
+        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);
+      else
+        ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);
+      if (!ok) continue;
+      float v = D;
+      if (flags & VAR_TN) {
+        v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);
+        if (!(v <= thr[bid[c]])) continue;
+      }
+      if (bestc < 0 || v < bestv) {
+        bestv = v;
+        bestc = c;
+      }
+    }
+    if (bestc < 0) {
+      labels[f] = -1;
+      dists[f] = INFINITY;
+    } else {
+      labels[f] = bid[bestc];
+      dists[f] = (flags & VAR_TN) ? bestv : sqrtf(bestv);
+    }
+    if (best) best[f] = (int32_t)bestc;
+  }
+  free(lc);
+  free(t2);
+  return 0;
 }
 
 /* ---------------------------------------------------------------- float64 */

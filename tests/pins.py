@@ -16,7 +16,7 @@ import math
 import numpy as np
 
 import exact_fp32 as X
-from oracle import BRUTE, CUT
+from oracle import BRUTE, CUT, DIR, TN
 from oracle import np_fp64
 
 F32 = np.float32
@@ -314,6 +314,156 @@ def pin_f32_vs_f64(O, seed=11):
     assert np.allclose(d32[ok].astype(np.float64), d64[ok], rtol=1e-6, atol=0)
 
 
+# ------------------------------------------------------------ metric variants
+def _line(length, n=21):
+    """Straight polyline along x, centered at the origin, spacing length / 20."""
+    p = np.zeros((n, 3), F32)
+    p[:, 0] = (np.arange(n) - 10) * (length / 20.0)
+    return p
+
+
+def pin_tn_closed_form(O):
+    """Collinear centered lines of lengths L and L' (spacings exact in float):
+    d_ME = |L - L'| / 2, TN = (|L - L'| / max + 1)^2 - 1, metric = d_ME + TN."""
+    for L, Lc, dme, tn in [(40.0, 20.0, 10.0, 1.25), (40.0, 30.0, 5.0, 0.5625),
+                           (40.0, 10.0, 15.0, 2.0625), (20.0, 40.0, 10.0, 1.25)]:
+        a, b = _line(L), _line(Lc)
+        assert O.arc_length_f32(a) == L and O.arc_length_f32(b) == Lc
+        assert O.tn_f32(L, Lc) == tn
+        bid = np.zeros(1, np.int32)
+        for fib in (a, a[::-1].copy()):
+            for T, ok in [(dme + tn + 0.25, True), (dme + tn - 0.25, False)]:
+                for mode in (BRUTE, CUT):
+                    lab, dist, _ = O.segment_ext_f32(fib[None], b[None], bid,
+                                                     np.array([T], F32), TN, mode=mode)
+                    if ok:
+                        assert lab[0] == 0 and dist[0] == dme + tn
+                    else:
+                        assert lab[0] == -1 and np.isinf(dist[0])
+                # without the length term the pair is accepted at d_ME
+                lab, dist, _ = O.segment_ext_f32(fib[None], b[None], bid,
+                                                 np.array([dme + tn - 0.25], F32), 0)
+                assert lab[0] == 0 and dist[0] == dme
+
+
+def pin_tn_properties(O, seed=12):
+    """TN is symmetric, zero for equal lengths, in [0, 3]; the length-normalised
+    labels are a subset of the plain ones with no smaller distance; integer
+    translates (identical lengths) keep their plain result."""
+    rng = np.random.default_rng(seed)
+    for _ in range(200):
+        ls, lc = (rng.uniform(1, 200, 2)).astype(F32)
+        t = O.tn_f32(float(ls), float(lc))
+        assert t == O.tn_f32(float(lc), float(ls))
+        assert 0.0 <= t <= 3.0
+        assert O.tn_f32(float(ls), float(ls)) == 0.0
+    assert O.tn_f32(0.0, 0.0) == 0.0
+    fib, cen, bid, thr = _random_set(rng, 150, 25, 5, near=0.7)
+    l0, d0, _ = O.segment_f32(fib, cen, bid, thr, mode=BRUTE)
+    l1, d1, _ = O.segment_ext_f32(fib, cen, bid, thr, TN, mode=BRUTE)
+    lab = l1 >= 0
+    assert (l0[lab] >= 0).all() and (d1[lab] >= d0[lab]).all()
+    assert lab.sum() > 20
+    # integer curves and integer translations: equal lengths, TN = 0 for the source
+    cen_i = np.round(cen[:6] / 4.0).astype(F32) * 4.0
+    shift = rng.integers(-2, 3, (6, 3)).astype(F32)
+    fib_i = cen_i + shift[:, None, :]
+    bid_i = np.arange(6, dtype=np.int32)
+    thr_i = np.full(6, 5.0, F32)
+    l0, d0, b0 = O.segment_f32(fib_i, cen_i, bid_i, thr_i, mode=BRUTE)
+    l1, d1, b1 = O.segment_ext_f32(fib_i, cen_i, bid_i, thr_i, TN, mode=BRUTE)
+    same = b0 == np.arange(6)
+    assert same.sum() >= 4
+    assert np.array_equal(l1[same], l0[same]) and np.array_equal(d1[same], d0[same])
+
+
+def pin_variants_cut_equals_brute(O, seed=13):
+    """Each variant reaches the same result by the paper's progressive discard
+    as by its brute-force definition; no flags is the plain decision."""
+    rng = np.random.default_rng(seed)
+    fib, cen, bid, thr = _random_set(rng, 200, 40, 8, near=0.6)
+    base = O.segment_f32(fib, cen, bid, thr, mode=BRUTE)
+    e0 = O.segment_ext_f32(fib, cen, bid, thr, 0, mode=CUT)
+    assert all(np.array_equal(x, y) for x, y in zip(base, e0))
+    for flags in (TN, DIR, TN | DIR):
+        a = O.segment_ext_f32(fib, cen, bid, thr, flags, mode=BRUTE)
+        b = O.segment_ext_f32(fib, cen, bid, thr, flags, mode=CUT)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), flags
+
+
+def _arc(radius, span_deg, center=(100.0, 100.0, 100.0), n=21, start_deg=0.0):
+    th = np.deg2rad(start_deg + np.arange(n) * span_deg / (n - 1))
+    p = np.zeros((n, 3))
+    p[:, 0] = center[0] + radius * np.cos(th)
+    p[:, 1] = center[1] + radius * np.sin(th)
+    p[:, 2] = center[2]
+    return p.astype(F32)
+
+
+def pin_dir_closed_form(O):
+    """A 300-degree arc b and the fiber a with b's end points but its interior in
+    the inverse order: the end points choose the direct order, whose largest
+    distance is the widest interior chord (the diameter, 2R), while Eq. 2 takes
+    the inverse order, whose largest distance is the end-point chord (R)."""
+    R = 20.0
+    b = _arc(R, 300.0)
+    a = b.copy()
+    a[1:20] = b[19:0:-1]
+    bid = np.zeros(1, np.int32)
+    pa, pb = a.astype(np.float64), b.astype(np.float64)
+    d_dir = max(((pa[i] - pb[i]) ** 2).sum() for i in range(21))
+    d_inv = max(((pa[i] - pb[20 - i]) ** 2).sum() for i in range(21))
+    assert abs(math.sqrt(d_dir) - 2 * R) < 1e-3 and abs(math.sqrt(d_inv) - R) < 1e-3
+    for T in (25.0, 45.0):
+        thr = np.array([T], F32)
+        for mode in (BRUTE, CUT):
+            le, de, _ = O.segment_ext_f32(a[None], b[None], bid, thr, 0, mode=mode)
+            ld, dd, _ = O.segment_ext_f32(a[None], b[None], bid, thr, DIR, mode=mode)
+            assert le[0] == 0 and abs(de[0] - math.sqrt(d_inv)) <= 1e-5 * R
+            if T < 2 * R:
+                assert ld[0] == -1 and np.isinf(dd[0])
+            else:
+                assert ld[0] == 0 and abs(dd[0] - math.sqrt(d_dir)) <= 1e-5 * 2 * R
+
+
+def pin_dir_tie_direct(O):
+    """A closed loop centroid (b_0 = b_20) ties the end-point test of any fiber;
+    the tie takes the direct order."""
+    b = _arc(15.0, 360.0)
+    b[20] = b[0]
+    a = b.copy()
+    a[1:20] = b[19:0:-1]  # interior in the inverse order: direct order is far off
+    a += F32(0.5)
+    bid = np.zeros(1, np.int32)
+    thr = np.array([100.0], F32)
+    pa, pb = a.astype(np.float64), b.astype(np.float64)
+    d_dir = max(((pa[i] - pb[i]) ** 2).sum() for i in range(21))
+    d_inv = max(((pa[i] - pb[20 - i]) ** 2).sum() for i in range(21))
+    assert d_dir > 4 * d_inv
+    for mode in (BRUTE, CUT):
+        ld, dd, _ = O.segment_ext_f32(a[None], b[None], bid, thr, DIR, mode=mode)
+        assert ld[0] == 0 and abs(dd[0] - math.sqrt(d_dir)) <= 1e-5 * math.sqrt(d_dir)
+
+
+def pin_dir_consistent_copies(O, seed=14):
+    """Noisy copies (either order) of well-separated open curves: the end points
+    pick the order Eq. 2 takes, so direction inference changes nothing."""
+    rng = np.random.default_rng(seed)
+    cen = np.stack([_smooth_curve(rng, rng.uniform(60, 120),
+                                  rng.uniform([20, 20, 20], [120, 160, 120])) for _ in range(12)])
+    bid = np.arange(12, dtype=np.int32)
+    thr = np.full(12, 3.0, F32)
+    fib = []
+    for i in range(120):
+        f = cen[i % 12].astype(np.float64) + rng.normal(0, 0.3, (21, 3))
+        fib.append((f[::-1] if i % 2 else f).astype(F32))
+    fib = np.stack(fib)
+    e = O.segment_ext_f32(fib, cen, bid, thr, 0, mode=BRUTE)
+    d = O.segment_ext_f32(fib, cen, bid, thr, DIR, mode=BRUTE)
+    assert (e[0] >= 0).mean() > 0.9
+    assert all(np.array_equal(x, y) for x, y in zip(e, d))
+
+
 ALL_PINS = [
     pin_expression_rounding,
     pin_straight_translation,
@@ -328,4 +478,10 @@ ALL_PINS = [
     pin_cut_equals_brute,
     pin_f64_vs_numpy,
     pin_f32_vs_f64,
+    pin_tn_closed_form,
+    pin_tn_properties,
+    pin_variants_cut_equals_brute,
+    pin_dir_closed_form,
+    pin_dir_tie_direct,
+    pin_dir_consistent_copies,
 ]

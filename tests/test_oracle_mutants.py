@@ -40,6 +40,18 @@ MUTANTS = {
                           "if (i == CENTER || i == 4 || i == 8 || i == 12 || i == 16 || i == 7) continue;\n    float x"),
     "f64_rounded_difference": ("double dx = (double)a[0] - (double)b[0];", "double dx = (double)(a[0] - b[0]);"),
     "f64_exclusive_threshold": ("if (d <= t * t && (bestc < 0 || d < bestd))", "if (d < t * t && (bestc < 0 || d < bestd))"),
+    "tn_not_squared": ("float uu = u * u;", "float uu = u;"),
+    "tn_min_length": ("float mx = ls > lc ? ls : lc;", "float mx = ls < lc ? ls : lc;"),
+    "tn_not_added": ("v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);", "v = sqrtf(D);"),
+    "tn_squared_metric": ("v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);", "v = D + oracle_tn_f32(ls, lc[c]);"),
+    "tn_threshold_ignored": ("if (!(v <= thr[bid[c]])) continue;", "(void)0;"),
+    "tn_arc_skips_segment": ("for (int i = 0; i + 1 < NP; ++i) {\n    float dx = p[3 * (i + 1)] - p[3 * i];",
+                             "for (int i = 1; i + 1 < NP; ++i) {\n    float dx = p[3 * (i + 1)] - p[3 * i];"),
+    "tn_distance_is_dme": ("dists[f] = (flags & VAR_TN) ? bestv : sqrtf(bestv);", "dists[f] = sqrtf(bestv);"),
+    "dir_tie_inverse": ("int direct = ed <= ei;\n  float mx = 0.0f;", "int direct = ed < ei;\n  float mx = 0.0f;"),
+    "dir_picks_larger": ("int direct = ed <= ei;\n  float mx = direct ? ed : ei;", "int direct = ed > ei;\n  float mx = direct ? ed : ei;"),
+    "dir_ignored_brute": ("if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);",
+                          "if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);"),
 }
 
 
