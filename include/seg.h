@@ -77,6 +77,25 @@ typedef enum seg_mode {
   SEG_PREFILTER_BF16_ORIENTED = 5
 } seg_mode;
 
+/* Metric variants of the paper (seg_options.metric):
+ *   SEG_METRIC_LENGTH_NORM  section 2.3, Eq. 3: a pair with D <= T2 is kept
+ *     when d_ME + TN <= T, TN = (|l_S - l_C| / max(l_S, l_C) + 1)^2 - 1 with
+ *     l the arc length of the 21-point polyline (segment lengths
+ *     sqrtf(fma(dz, dz, fma(dy, dy, dx * dx))) summed in point order, TN = 0
+ *     for two zero lengths, each step rounded to float32); fibers take the
+ *     bundle of the smallest d_ME + TN (sqrtf(D) + TN, rounded once), which
+ *     is also the reported distance;
+ *   SEG_METRIC_DIRECTION  section 2.4, "Inference of fiber direction": the
+ *     point order with the smaller largest end-point distance (direct on a
+ *     tie) is the fiber's direction, and D is the largest point distance of
+ *     that order alone (instead of the smaller of the two orders).
+ * Both keep every cut of every mode exact: each accepted pair has
+ * min(D_direct, D_inverse) <= T2. */
+typedef enum seg_metric {
+  SEG_METRIC_LENGTH_NORM = 1,
+  SEG_METRIC_DIRECTION = 2
+} seg_metric;
+
 typedef struct seg_options {
   int32_t mode;          /* seg_mode; default SEG_PLAIN */
   int32_t validate;      /* 1: check inputs on the device and synchronise the
@@ -99,6 +118,8 @@ typedef struct seg_options {
                             after the launch of the mode's dominant kernel
                             (on `stream`), so a caller can time that kernel
                             alone; NULL = no events */
+  int32_t metric;        /* 0 or an OR of seg_metric flags (every mode and
+                            the batch path take them) */
 } seg_options;
 
 typedef struct seg_stats {

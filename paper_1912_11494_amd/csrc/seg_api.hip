@@ -42,6 +42,7 @@ struct AtlasBuf {
   float* cprep = nullptr;   // [m_pad][64]
   float4* ccen = nullptr;   // [m_pad]
   int32_t* bid = nullptr;   // [m_pad]
+  float* cext = nullptr;    // [m_pad][2]: arc length, threshold T
   int64_t cap = 0;          // capacity in centroids
   int64_t m = 0;
 
@@ -51,6 +52,7 @@ struct AtlasBuf {
     HIP_TRY(hipMalloc(&cprep, (size_t)mp * seg::CREC_BYTES));
     HIP_TRY(hipMalloc(&ccen, (size_t)mp * sizeof(float4)));
     HIP_TRY(hipMalloc(&bid, (size_t)mp * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&cext, (size_t)mp * 2 * sizeof(float)));
     cap = mp;
     return 0;
   }
@@ -58,9 +60,11 @@ struct AtlasBuf {
     if (cprep) (void)hipFree(cprep);
     if (ccen) (void)hipFree(ccen);
     if (bid) (void)hipFree(bid);
+    if (cext) (void)hipFree(cext);
     cprep = nullptr;
     ccen = nullptr;
     bid = nullptr;
+    cext = nullptr;
     cap = 0;
   }
 };
@@ -164,6 +168,12 @@ int check_mode(int mode) {
   }
 }
 
+int check_metric(int flags) {
+  if (flags & ~(SEG_METRIC_LENGTH_NORM | SEG_METRIC_DIRECTION))
+    return fail(SEG_EINVAL, "unknown metric flag");
+  return 0;
+}
+
 int check_atlas_args(const float* centroids, int64_t m, const int32_t* bid, const float* thr,
                      int32_t nb) {
   if (m < 0) return fail(SEG_EINVAL, "n_centroids < 0");
@@ -182,7 +192,7 @@ int prepare_atlas(AtlasBuf& ab, const float* centroids, int64_t m, const int32_t
   int rc = ab.reserve(pad8(m > 0 ? m : 1));
   if (rc) return rc;
   ab.m = m;
-  if (seg::launch_prep_atlas(centroids, m, bid, thr, nb, ab.cprep, ab.ccen, ab.bid,
+  if (seg::launch_prep_atlas(centroids, m, bid, thr, nb, ab.cprep, ab.ccen, ab.bid, ab.cext,
                              (unsigned int*)flags, s))
     return hip_fail(hipGetLastError(), "prep_atlas launch");
   return 0;
@@ -216,22 +226,23 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
   const int32_t m = (int32_t)ab.m;
   hipEvent_t* ev = (hipEvent_t*)o.profile_events;
   const int tile = o.tile ? o.tile : tuned_tile(o.mode, n, m);
+  const seg::Metric mt{ab.cext, o.metric};
   int rc = 0;
   switch (o.mode) {
     case SEG_DENSE:
       if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-      rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, tile, s);
+      rc = seg::launch_dense(fibers, n, ab.cprep, m, ab.bid, labels, dists, tile, mt, s);
       if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     case SEG_PLAIN:
       if (ev) HIP_TRY(hipEventRecord(ev[0], s));
       rc = seg::launch_plain(fibers, n, ab.ccen, ab.cprep, m, ab.bid, labels, dists, counters,
-                             tile, s);
+                             tile, mt, s);
       if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     default:
       rc = seg::run_prefilter(o.mode, tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
-                              dists, counters, sc->pre, ev, s);
+                              dists, counters, mt, sc->pre, ev, s);
       if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
       break;
   }
@@ -267,6 +278,7 @@ void seg_default_options(seg_options* opt) {
   opt->tile = 0;
   opt->collect_stats = 0;
   opt->profile_events = nullptr;
+  opt->metric = 0;
 }
 
 const char* seg_last_error(void) { return t_err.c_str(); }
@@ -279,6 +291,7 @@ int seg_segment(const float* fibers, int64_t n, const float* centroids, int64_t 
   t_err.clear();
   const seg_options o = resolve(opt);
   int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
   if (rc) return rc;
   if (n < 0) return fail(SEG_EINVAL, "n_fibers < 0");
   rc = check_atlas_args(centroids, m, bid, thr, nb);
@@ -369,6 +382,7 @@ int seg_segment_atlas(const seg_atlas* a, const float* fibers, int64_t n, int32_
   if (!a) return fail(SEG_EINVAL, "null atlas");
   const seg_options o = resolve(opt);
   int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
   if (rc) return rc;
   if (n < 0) return fail(SEG_EINVAL, "n_fibers < 0");
   if (n > 0 && (!fibers || !labels || !dists)) return fail(SEG_EINVAL, "null fiber/output pointer");
@@ -406,6 +420,7 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
     return fail(SEG_EINVAL, "null batch array");
   const seg_options o = resolve(opt);
   int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
   if (rc) return rc;
   for (int32_t a = 0; a < n_atlases; ++a)
     if (!atlases[a]) return fail(SEG_EINVAL, "null atlas in batch");
@@ -423,13 +438,14 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
   std::vector<seg::BatchAtlas> bav;
   for (int32_t a = 0; a < n_atlases; ++a)
     bav.push_back(seg::BatchAtlas{atlases[a]->buf.cprep, atlases[a]->buf.ccen,
-                                  atlases[a]->buf.bid, (int32_t)atlases[a]->buf.m});
+                                  atlases[a]->buf.bid, atlases[a]->buf.cext,
+                                  (int32_t)atlases[a]->buf.m});
   int64_t nmax = 0, mmax = 0;
   for (int32_t i = 0; i < n_subjects; ++i) nmax = n_fibers[i] > nmax ? n_fibers[i] : nmax;
   for (const auto& a : bav) mmax = a.m > mmax ? a.m : mmax;
   const int tile = o.tile ? o.tile : tuned_tile(o.mode, nmax, mmax);
   rc = seg::run_batch(o.mode, tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
-                      dists, sc->batch, sc->pre, s);
+                      dists, o.metric, sc->batch, sc->pre, s);
   if (rc == -2) return fail(SEG_EMODE, "mode not supported by the batch path");
   if (rc == -3) return fail(SEG_ENOMEM, "batch scratch allocation failed");
   if (rc) return hip_fail(hipGetLastError(), "batch launch");

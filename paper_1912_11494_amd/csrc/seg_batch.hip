@@ -14,16 +14,16 @@ namespace seg {
 
 int run_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
               const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
-              int32_t* const* labels, float* const* dists, BatchBuf& bb, PrefilterBuf& pb,
-              hipStream_t s) {
+              int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
+              PrefilterBuf& pb, hipStream_t s) {
   (void)pb;
   if (n_atlases == 0 || n_subjects == 0) return 0;
   if (mode == 1)
-    return plain_batch(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels, dists, bb,
-                       s);
+    return plain_batch(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels, dists,
+                       mflags, bb, s);
   if (mode >= 2 && mode <= 5)
     return prefilter_batch(mode, cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
-                           dists, bb, s);
+                           dists, mflags, bb, s);
   return -2;  // the dense pass has no batched form
 }
 

@@ -416,8 +416,9 @@ struct CullJob {
 // largest point distance of each order, an order dying on a point above T2
 // as in the exact stage, D the smaller maximum of the live orders.  Every
 // point is evaluated (no early exit); the accepted set and D equal those of
-// exact_pair.
-__device__ __forceinline__ bool dense_pair(const float* a, const float* b, float t2, float& D) {
+// exact_pair (with the same metric flags).
+__device__ __forceinline__ bool dense_pair(const float* a, const float* b, float t2, float& D,
+                                           int flags) {
   float md = 0.0f, mi = 0.0f;
   bool ad = true, ai = true;
 #pragma unroll
@@ -429,6 +430,16 @@ __device__ __forceinline__ bool dense_pair(const float* a, const float* b, float
     ai = ai && y <= t2;
     md = fmaxf(md, x);
     mi = fmaxf(mi, y);
+  }
+  if (flags & MF_DIR) {
+    // the order with the smaller largest end-point distance (direct on ties)
+    const float x0 = d2(a[0], a[1], a[2], b[0], b[1], b[2]);
+    const float x1 = d2(a[60], a[61], a[62], b[60], b[61], b[62]);
+    const float y0 = d2(a[0], a[1], a[2], b[60], b[61], b[62]);
+    const float y1 = d2(a[60], a[61], a[62], b[0], b[1], b[2]);
+    const bool direct = fmaxf(x0, x1) <= fmaxf(y0, y1);
+    ad = ad && direct;
+    ai = ai && !direct;
   }
   D = ad ? (ai ? fminf(md, mi) : md) : mi;
   return ad || ai;
@@ -452,7 +463,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
                                                          const float* __restrict__ fibers,
                                                          const float* __restrict__ cprep,
                                                          unsigned long long* __restrict__ keys,
-                                                         unsigned long long* __restrict__ counters) {
+                                                         unsigned long long* __restrict__ counters,
+                                                         Metric mt) {
   StageCounts sc{counters};
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves) return;
@@ -468,10 +480,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
       e = act ? make_int2(perm[e.x], e.y) : make_int2(0, 0);
       const float* ar = fibers + (int64_t)e.x * NF;
       const float* br = cprep + (size_t)e.y * CREC;
-      float D;
+      float D, v;
       bool ok;
       if (STATS) {
-        ok = exact_pair<true>(ar, br, act, D, sc);
+        ok = exact_pair<true>(ar, br, act, D, sc, mt.flags);
       } else {
         float a[NF], b[CREC];
 #pragma unroll
@@ -493,9 +505,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
           b[4 * k + 2] = v.z;
           b[4 * k + 3] = v.w;
         }
-        ok = act && dense_pair(a, b, b[NF], D);
+        ok = act && dense_pair(a, b, b[NF], D, mt.flags);
       }
-      if (ok) atomicMin(&keys[e.x], (unsigned long long)make_key(D, (uint32_t)e.y));
+      if (ok && variant_value(D, (uint32_t)e.y, (mt.flags & MF_TN) ? arc_length(ar) : 0.0f, mt, v))
+        atomicMin(&keys[e.x], (unsigned long long)make_key(v, (uint32_t)e.y));
     }
   };
   const uint32_t cnt = list_n[w];
@@ -518,7 +531,8 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
                                                      const float* __restrict__ fibers,
                                                      const float* __restrict__ cprep, int32_t m,
                                                      unsigned long long* __restrict__ keys,
-                                                     unsigned long long* __restrict__ counters) {
+                                                     unsigned long long* __restrict__ counters,
+                                                     Metric mt) {
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves || !(list_n[w] & RESCUE)) return;
   unsigned long long naccepted = 0;
@@ -529,14 +543,17 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
   const float* ar = fibers + f * NF;
 #pragma unroll
   for (int k = 0; k < NF; ++k) a[k] = ar[k];
+  const float ls = (mt.flags & MF_TN) ? arc_length(a) : 0.0f;
   unsigned long long best = NO_KEY;
   for (int32_t c = 0; c < m; ++c) {
     const float* b = cprep + (size_t)c * CREC;  // the same for every lane
-    float D;
-    if (act && dense_pair(a, b, b[NF], D)) {
-      const unsigned long long k = make_key(D, (uint32_t)c);
-      best = k < best ? k : best;
+    float D, v;
+    if (act && dense_pair(a, b, b[NF], D, mt.flags)) {
       ++naccepted;
+      if (variant_value(D, (uint32_t)c, ls, mt, v)) {
+        const unsigned long long k = make_key(v, (uint32_t)c);
+        best = k < best ? k : best;
+      }
     }
   }
   if (act) keys[f] = best;
@@ -547,9 +564,9 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void finalize_kernel(const unsigned long long* __restrict__ keys,
                                                        int64_t n, const int32_t* __restrict__ bid,
                                                        int32_t* __restrict__ labels,
-                                                       float* __restrict__ dists) {
+                                                       float* __restrict__ dists, int flags) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < n) write_result(keys[f], bid, labels + f, dists + f);
+  if (f < n) write_result(keys[f], bid, labels + f, dists + f, flags);
 }
 
 __global__ __launch_bounds__(256) void fill_u64_n_kernel(unsigned long long* __restrict__ p,
@@ -867,8 +884,8 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
 
 template <int Q>
 int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, const int32_t* bid,
-                int32_t* labels, float* dists, unsigned long long* counters, PrefilterBuf& pb,
-                hipEvent_t* ev, hipStream_t s) {
+                int32_t* labels, float* dists, unsigned long long* counters, Metric mt,
+                PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
   constexpr int EB = QTraits<Q>::bytes;
   const int64_t n_pad = (n + 255) / 256 * 256;
   const int32_t ncols_pad = (m + 31) / 32 * 32;
@@ -936,17 +953,17 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
   if (counters)
     exact_list_kernel<true, CULL_QCAP><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters);
+        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt);
   else
     exact_list_kernel<false, CULL_QCAP><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters);
+        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt);
   if (counters)
     rescue_kernel<true><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys,
-                                               counters);
+                                               counters, mt);
   else
     rescue_kernel<false><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m,
-                                                fkeys, counters);
-  finalize_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, bid, labels, dists);
+                                                fkeys, counters, mt);
+  finalize_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, bid, labels, dists, mt.flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -954,13 +971,13 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
 
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
   if (n <= 0) return 0;
   if (n >= ((int64_t)1 << 31)) return -2;  // sorted rows are indexed with 32 bits
   switch (q) {
-    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, pb, ev, s);
-    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, pb, ev, s);
-    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, pb, ev, s);
+    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
+    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
+    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
     default: return -2;
   }
 }

@@ -30,6 +30,57 @@ __device__ __forceinline__ float d2(float ax, float ay, float az, float bx, floa
 // Squared bundle threshold; -1 makes every comparison d2 <= T2 false.
 __device__ __forceinline__ float thr2(float t) { return t >= 0.0f ? t * t : -1.0f; }
 
+// Metric variants.  MF_TN: length normalisation (Eq. 3) -- an accepted pair
+// (D <= T2) is kept when d_ME + TN <= T, and fibers take the bundle of the
+// smallest d_ME + TN, which is also the reported distance.  MF_DIR: direction
+// inference (section 2.4) -- the order with the smaller largest end-point
+// distance (direct on ties) is the fiber's direction and D is the largest
+// point distance of that order alone.
+constexpr int MF_TN = 1;
+constexpr int MF_DIR = 2;
+struct Metric {
+  const float* cext;  // per prepared centroid: arc length, threshold T
+  int32_t flags;
+};
+
+// Arc length of a 21-point polyline: segment lengths
+// sqrtf(fma(dz, dz, fma(dy, dy, dx * dx))) of p[i+1] - p[i], summed in order.
+__device__ __forceinline__ float arc_length(const float* __restrict__ p) {
+  float l = 0.0f;
+#pragma unroll
+  for (int i = 0; i + 1 < NP; ++i) {
+    const float dx = p[3 * (i + 1)] - p[3 * i];
+    const float dy = p[3 * (i + 1) + 1] - p[3 * i + 1];
+    const float dz = p[3 * (i + 1) + 2] - p[3 * i + 2];
+    l = l + sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+  }
+  return l;
+}
+
+// TN of Eq. 3: (|lS - lC| / max(lS, lC) + 1)^2 - 1, each step rounded; 0 when
+// both lengths are 0.
+__device__ __forceinline__ float tn_term(float ls, float lc) {
+  const float mx = ls > lc ? ls : lc;
+  if (!(mx > 0.0f)) return 0.0f;
+  const float r = fabsf(ls - lc) / mx;
+  const float u = r + 1.0f;
+  const float uu = u * u;
+  return uu - 1.0f;
+}
+
+// Value the argmin compares for an accepted pair (D <= T2): D itself, or with
+// MF_TN the complete metric sqrtf(D) + TN, which must not exceed T (else the
+// pair is dropped).  `ls` is the fiber's arc length (MF_TN only).
+__device__ __forceinline__ bool variant_value(float D, uint32_t c, float ls, const Metric& mt,
+                                              float& v) {
+  if (!(mt.flags & MF_TN)) {
+    v = D;
+    return true;
+  }
+  v = sqrtf(D) + tn_term(ls, mt.cext[2 * c]);
+  return v <= mt.cext[2 * c + 1];
+}
+
 // Argmin key: D >= +0, so its bit pattern orders like the value; the low
 // word breaks ties towards the lower centroid index.
 __device__ __forceinline__ uint64_t make_key(float D, uint32_t c) {
@@ -97,7 +148,7 @@ struct StageCounts {
 template <bool STATS>
 __device__ __forceinline__ bool exact_pair(const float* __restrict__ a,
                                            const float* __restrict__ b, bool active, float& D,
-                                           StageCounts sc) {
+                                           StageCounts sc, int flags = 0) {
   const float t2 = b[NF];
   // test1: center point (orientation-free)
   float c = d2(ld(a, CTR), ld(b, CTR));
@@ -111,6 +162,12 @@ __device__ __forceinline__ bool exact_pair(const float* __restrict__ a,
     float y0 = d2(a0, b20), y1 = d2(a20, b0);
     ad = ad && x0 <= t2 && x1 <= t2;
     ai = ai && y0 <= t2 && y1 <= t2;
+    if (flags & MF_DIR) {
+      // the end points fix the direction; the other order is dropped
+      const bool direct = fmaxf(x0, x1) <= fmaxf(y0, y1);
+      ad = ad && direct;
+      ai = ai && !direct;
+    }
     md = fmaxf(md, fmaxf(x0, x1));
     mi = fmaxf(mi, fmaxf(y0, y1));
   }
@@ -182,7 +239,8 @@ __device__ __forceinline__ void queue_push(WaveQueue wq, uint32_t& n, uint64_t m
 template <bool STATS>
 __device__ __forceinline__ void queue_drain_body(WaveQueue wq, uint32_t n,
                                             const float* __restrict__ fib_base,
-                                            const float* __restrict__ cprep, StageCounts sc) {
+                                            const float* __restrict__ cprep, StageCounts sc,
+                                            Metric mt) {
   const uint32_t lane = lane_id();
   if (STATS && lane == 0) {
     atomicAdd(sc.p + 0, (unsigned long long)n);
@@ -194,18 +252,20 @@ __device__ __forceinline__ void queue_drain_body(WaveQueue wq, uint32_t n,
     const uint32_t e = act ? wq.q[j] : 0u;
     const uint32_t slot = e & 0xffu;
     const uint32_t c = e >> 8;
-    float D;
-    bool ok = exact_pair<STATS>(fib_base + (size_t)slot * NF, cprep + (size_t)c * CREC, act, D,
-                                sc);
-    if (ok) atomicMin((unsigned long long*)&wq.keys[slot], (unsigned long long)make_key(D, c));
+    float D, v;
+    const float* a = fib_base + (size_t)slot * NF;
+    bool ok = exact_pair<STATS>(a, cprep + (size_t)c * CREC, act, D, sc, mt.flags);
+    if (ok && variant_value(D, c, (mt.flags & MF_TN) ? arc_length(a) : 0.0f, mt, v))
+      atomicMin((unsigned long long*)&wq.keys[slot], (unsigned long long)make_key(v, c));
   }
 }
 
 template <bool STATS>
 __device__ __forceinline__ void queue_drain(WaveQueue wq, uint32_t n,
                                             const float* __restrict__ fib_base,
-                                            const float* __restrict__ cprep, StageCounts sc) {
-  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc);
+                                            const float* __restrict__ cprep, StageCounts sc,
+                                            Metric mt) {
+  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc, mt);
 }
 
 // The same as a real call: drains are rare, and keeping the exact stage out
@@ -214,20 +274,24 @@ __device__ __forceinline__ void queue_drain(WaveQueue wq, uint32_t n,
 template <bool STATS>
 __device__ __noinline__ void queue_drain_call(WaveQueue wq, uint32_t n,
                                               const float* __restrict__ fib_base,
-                                              const float* __restrict__ cprep, StageCounts sc) {
-  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc);
+                                              const float* __restrict__ cprep, StageCounts sc,
+                                              Metric mt) {
+  queue_drain_body<STATS>(wq, n, fib_base, cprep, sc, mt);
 }
 
-// Final write of one fiber from its argmin key.
+// Final write of one fiber from its argmin key: the key holds D (the
+// distance is sqrtf(D)) or, with MF_TN, the complete metric itself.
 __device__ __forceinline__ void write_result(uint64_t key, const int32_t* __restrict__ bid,
-                                             int32_t* __restrict__ label, float* __restrict__ dist) {
+                                             int32_t* __restrict__ label, float* __restrict__ dist,
+                                             int flags = 0) {
   if (key == NO_KEY) {
     *label = -1;
     *dist = __builtin_inff();
   } else {
     const uint32_t c = (uint32_t)key;
+    const float v = __uint_as_float((uint32_t)(key >> 32));
     *label = bid[c];
-    *dist = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    *dist = (flags & MF_TN) ? v : sqrtf(v);
   }
 }
 

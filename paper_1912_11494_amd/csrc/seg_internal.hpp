@@ -6,6 +6,8 @@
 
 #include <vector>
 
+#include "seg_device.hpp"
+
 namespace seg {
 
 constexpr unsigned int FLAG_BUNDLE = 1u;
@@ -66,21 +68,23 @@ struct BatchAtlas {
   const float* cprep;
   const float4* ccen;
   const int32_t* bid;
+  const float* cext;  // per centroid: arc length, threshold (metric variants)
   int32_t m;
 };
 
 int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const float* thr,
-                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out,
+                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out, float* cext,
                       unsigned int* flags, hipStream_t s);
 int launch_check_finite(const float* v, int64_t count, unsigned int* flags, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 int launch_fill_empty(int64_t n, int32_t* labels, float* dists, hipStream_t s);
 int launch_dense(const float* fibers, int64_t n, const float* cprep, int32_t m,
-                 const int32_t* bid, int32_t* labels, float* dists, int cfg, hipStream_t s);
+                 const int32_t* bid, int32_t* labels, float* dists, int cfg, Metric mt,
+                 hipStream_t s);
 int plain_default_cfg(int64_t n);
 int launch_plain(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
                  int32_t m, const int32_t* bid, int32_t* labels, float* dists,
-                 unsigned long long* counters, int cfg, hipStream_t s);
+                 unsigned long long* counters, int cfg, Metric mt, hipStream_t s);
 int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32_t m,
                        int32_t* pairs, int64_t cap, unsigned long long* count, hipStream_t s);
 
@@ -88,8 +92,8 @@ int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32
 // unsupported mode or tile, -3 on a failed allocation.
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
-                  float* dists, unsigned long long* counters, PrefilterBuf& pb, hipEvent_t* ev,
-                  hipStream_t s);
+                  float* dists, unsigned long long* counters, Metric mt, PrefilterBuf& pb,
+                  hipEvent_t* ev, hipStream_t s);
 // Frame set-up shared by the prefilter forms: reset the parameters and take
 // the bounding box of the atlas points (seg_prefilter.hip).
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
@@ -97,7 +101,7 @@ int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s)
 // Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s);
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s);
 
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,
@@ -108,15 +112,16 @@ int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep
 // changes) and run the whole batch as one cached HIP graph (seg_graph.hpp).
 int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
                     const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
-                    int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s);
+                    int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
+                    hipStream_t s);
 int plain_batch(int cfg, const BatchAtlas* atlases, int32_t n_atlases, const float* const* fibers,
                 const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
-                float* const* dists, BatchBuf& bb, hipStream_t s);
+                float* const* dists, int mflags, BatchBuf& bb, hipStream_t s);
 
 // Batched persistent launch (seg_batch.hip); same return codes.
 int run_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
               const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
-              int32_t* const* labels, float* const* dists, BatchBuf& bb, PrefilterBuf& pb,
-              hipStream_t s);
+              int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
+              PrefilterBuf& pb, hipStream_t s);
 
 }  // namespace seg

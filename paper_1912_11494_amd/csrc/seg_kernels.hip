@@ -31,6 +31,7 @@ __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict
                                                          float* __restrict__ cprep,
                                                          float4* __restrict__ ccen,
                                                          int32_t* __restrict__ bid_out,
+                                                         float* __restrict__ cext,
                                                          unsigned int* __restrict__ flags) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m) {
@@ -60,6 +61,9 @@ __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict
   if (!finite) atomicOr(flags, FLAG_NONFINITE);
   ccen[c] = make_float4(src[3 * CTR], src[3 * CTR + 1], src[3 * CTR + 2], t2);
   bid_out[c] = b;
+  // for the length-normalised metric: arc length and threshold T
+  cext[2 * c] = arc_length(dst);
+  cext[2 * c + 1] = (b >= 0 && b < nb) ? thr[b] : -1.0f;
 }
 
 __global__ __launch_bounds__(256) void check_thresholds_kernel(const float* __restrict__ thr,
@@ -104,16 +108,18 @@ __global__ __launch_bounds__(256) void fill_empty_kernel(int64_t n, int32_t* __r
 // 2 FMAs and a max per point distance).  The argmin stays in registers: the
 // centroid loop runs in increasing index order and a strictly smaller D
 // replaces the best, so equal distances keep the lower index.
-template <int FPL>
+template <int FPL, bool VAR>
 __global__ __launch_bounds__(256) void dense_kernel(const float* __restrict__ fibers, int64_t n,
                                                     const float* __restrict__ cprep, int32_t m,
                                                     const int32_t* __restrict__ bid,
                                                     int32_t* __restrict__ labels,
-                                                    float* __restrict__ dists) {
+                                                    float* __restrict__ dists, Metric mt) {
   const int64_t base = ((int64_t)blockIdx.x * blockDim.x) * FPL + threadIdx.x;
   float a[FPL][NF];
   float best[FPL];
   int32_t bc[FPL];
+  float ls[FPL];  // arc lengths (metric variants only)
+  uint64_t bkey[FPL];
 #pragma unroll
   for (int k = 0; k < FPL; ++k) {
     const int64_t f = base + (int64_t)k * blockDim.x;
@@ -122,6 +128,8 @@ __global__ __launch_bounds__(256) void dense_kernel(const float* __restrict__ fi
     for (int j = 0; j < NF; ++j) a[k][j] = src[j];
     best[k] = 0.0f;
     bc[k] = -1;
+    bkey[k] = NO_KEY;
+    ls[k] = VAR && (mt.flags & MF_TN) ? arc_length(a[k]) : 0.0f;
   }
   for (int32_t c = 0; c < m; ++c) {
     const float* b = cprep + (size_t)c * CREC;
@@ -142,18 +150,34 @@ __global__ __launch_bounds__(256) void dense_kernel(const float* __restrict__ fi
         md = fmaxf(md, x);
         mi = fmaxf(mi, y);
       }
-      const float D = fminf(md, mi);
-      const bool take = D <= t2 && (bc[k] < 0 || D < best[k]);
-      best[k] = take ? D : best[k];
-      bc[k] = take ? c : bc[k];
+      if (!VAR) {
+        const float D = fminf(md, mi);
+        const bool take = D <= t2 && (bc[k] < 0 || D < best[k]);
+        best[k] = take ? D : best[k];
+        bc[k] = take ? c : bc[k];
+      } else {
+        float D = fminf(md, mi);
+        if (mt.flags & MF_DIR) {
+          const float x0 = d2(a[k][0], a[k][1], a[k][2], b[0], b[1], b[2]);
+          const float x1 = d2(a[k][60], a[k][61], a[k][62], b[60], b[61], b[62]);
+          const float y0 = d2(a[k][0], a[k][1], a[k][2], b[60], b[61], b[62]);
+          const float y1 = d2(a[k][60], a[k][61], a[k][62], b[0], b[1], b[2]);
+          D = fmaxf(x0, x1) <= fmaxf(y0, y1) ? md : mi;
+        }
+        float v;
+        if (D <= t2 && variant_value(D, (uint32_t)c, ls[k], mt, v)) {
+          const uint64_t key = make_key(v, (uint32_t)c);
+          bkey[k] = key < bkey[k] ? key : bkey[k];
+        }
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < FPL; ++k) {
     const int64_t f = base + (int64_t)k * blockDim.x;
     if (f < n) {
-      uint64_t key = bc[k] < 0 ? NO_KEY : make_key(best[k], (uint32_t)bc[k]);
-      write_result(key, bid, labels + f, dists + f);
+      uint64_t key = VAR ? bkey[k] : (bc[k] < 0 ? NO_KEY : make_key(best[k], (uint32_t)bc[k]));
+      write_result(key, bid, labels + f, dists + f, VAR ? mt.flags : 0);
     }
   }
 }
@@ -180,6 +204,7 @@ struct PlainJob {
   const int32_t* bid;
   int32_t* labels;
   float* dists;
+  Metric mt;
 };
 
 template <int FPL, int QCAP, bool STATS>
@@ -252,18 +277,18 @@ __device__ __forceinline__ void plain_block(const PlainJob& job, int64_t block,
         for (int k = 0; k < FPL; ++k)
           if (msk[u][k]) queue_push(wq, qn, msk[u][k], (c << 8) | (uint32_t)(k * 64 + lane));
         if (qn > (uint32_t)(QCAP - 64 * FPL)) {
-          queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
+          queue_drain<STATS>(wq, qn, fib_base, cprep, sc, job.mt);
           qn = 0;
         }
       }
     }
   }
-  queue_drain<STATS>(wq, qn, fib_base, cprep, sc);
+  queue_drain<STATS>(wq, qn, fib_base, cprep, sc, job.mt);
 
 #pragma unroll
   for (int k = 0; k < FPL; ++k) {
     const int64_t f = wbase + k * 64 + lane;
-    if (f < n) write_result(wq.keys[k * 64 + lane], bid, labels + f, dists + f);
+    if (f < n) write_result(wq.keys[k * 64 + lane], bid, labels + f, dists + f, job.mt.flags);
   }
 }
 
@@ -310,12 +335,12 @@ __global__ __launch_bounds__(256) void plain_pairs_kernel(const float* __restric
 // ---------------------------------------------------------------- launchers
 
 int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const float* thr,
-                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out,
+                      int32_t nb, float* cprep, float4* ccen, int32_t* bid_out, float* cext,
                       unsigned int* flags, hipStream_t s) {
   if (m > 0) {
     const int64_t mp = (m + 7) & ~(int64_t)7;
     prep_atlas_kernel<<<(unsigned)((mp + 255) / 256), 256, 0, s>>>(cen, m, bid, thr, nb, cprep,
-                                                                    ccen, bid_out, flags);
+                                                                    ccen, bid_out, cext, flags);
   }
   if (nb > 0) check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -340,26 +365,30 @@ int launch_fill_empty(int64_t n, int32_t* labels, float* dists, hipStream_t s) {
 }
 
 int launch_dense(const float* fibers, int64_t n, const float* cprep, int32_t m,
-                 const int32_t* bid, int32_t* labels, float* dists, int cfg, hipStream_t s) {
+                 const int32_t* bid, int32_t* labels, float* dists, int cfg, Metric mt,
+                 hipStream_t s) {
   // cfg 1: one fiber per lane; cfg 2: two fibers per lane
   const int fpl = cfg == 2 ? 2 : 1;
   const int64_t per_block = 256 * fpl;
   const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
-  if (fpl == 2)
-    dense_kernel<2><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists);
+  if (mt.flags)
+    dense_kernel<1, true><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fibers, n, cprep, m, bid,
+                                                                      labels, dists, mt);
+  else if (fpl == 2)
+    dense_kernel<2, false><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists, mt);
   else
-    dense_kernel<1><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists);
+    dense_kernel<1, false><<<blocks, 256, 0, s>>>(fibers, n, cprep, m, bid, labels, dists, mt);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int FPL>
 static void plain_launch(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
                          int32_t m, const int32_t* bid, int32_t* labels, float* dists,
-                         unsigned long long* counters, hipStream_t s) {
+                         unsigned long long* counters, Metric mt, hipStream_t s) {
   constexpr int per_block = 4 * 64 * FPL;
   const unsigned blocks = (unsigned)((n + per_block - 1) / per_block);
   constexpr int QCAP = 512;
-  const PlainJob job{fibers, n, ccen, cprep, m, bid, labels, dists};
+  const PlainJob job{fibers, n, ccen, cprep, m, bid, labels, dists, mt};
   if (counters)
     plain_kernel<FPL, QCAP, true><<<blocks, 256, 0, s>>>(job, counters);
   else
@@ -376,12 +405,12 @@ int plain_default_cfg(int64_t n) {
 
 int launch_plain(const float* fibers, int64_t n, const float4* ccen, const float* cprep,
                  int32_t m, const int32_t* bid, int32_t* labels, float* dists,
-                 unsigned long long* counters, int cfg, hipStream_t s) {
+                 unsigned long long* counters, int cfg, Metric mt, hipStream_t s) {
   if (cfg <= 0) cfg = plain_default_cfg(n);
   switch (cfg) {
-    case 1: plain_launch<1>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
-    case 2: plain_launch<2>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
-    case 4: plain_launch<4>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, s); break;
+    case 1: plain_launch<1>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, mt, s); break;
+    case 2: plain_launch<2>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, mt, s); break;
+    case 4: plain_launch<4>(fibers, n, ccen, cprep, m, bid, labels, dists, counters, mt, s); break;
     default: return -2;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -402,10 +431,10 @@ int grow_buf(void** p, size_t* have, size_t want) {
 template <int FPL>
 int plain_batch_cfg(int cfg, const BatchAtlas* at, int32_t na, const float* const* fibers,
                     const int64_t* nf, int32_t ns, int32_t* const* labels, float* const* dists,
-                    BatchBuf& bb, hipStream_t s) {
+                    int mflags, BatchBuf& bb, hipStream_t s) {
   constexpr int QCAP = 512;
   constexpr int64_t FPB = 4 * 64 * FPL;
-  std::vector<uint64_t> key = {1u, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns};
+  std::vector<uint64_t> key = {1u, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns, (uint64_t)mflags};
   for (int32_t a = 0; a < na; ++a) {
     key.push_back((uint64_t)(uintptr_t)at[a].ccen);
     key.push_back((uint64_t)at[a].m);
@@ -432,7 +461,8 @@ int plain_batch_cfg(int cfg, const BatchAtlas* at, int32_t na, const float* cons
       for (int32_t i = 0; i < ns; ++i) {
         if (nf[i] == 0) continue;
         jobs.push_back(PlainJob{fibers[i], nf[i], at[a].ccen, at[a].cprep, at[a].m, at[a].bid,
-                                labels[i * na + a], dists[i * na + a]});
+                                labels[i * na + a], dists[i * na + a],
+                                Metric{at[a].cext, mflags}});
         start.push_back(start.back() + (nf[i] + FPB - 1) / FPB);
       }
     }
@@ -472,18 +502,18 @@ int plain_batch_cfg(int cfg, const BatchAtlas* at, int32_t na, const float* cons
 
 int plain_batch(int cfg, const BatchAtlas* atlases, int32_t n_atlases, const float* const* fibers,
                 const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
-                float* const* dists, BatchBuf& bb, hipStream_t s) {
+                float* const* dists, int mflags, BatchBuf& bb, hipStream_t s) {
   switch (cfg) {
     case 0:
     case 4:
       return plain_batch_cfg<4>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
-                                dists, bb, s);
+                                dists, mflags, bb, s);
     case 1:
       return plain_batch_cfg<1>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
-                                dists, bb, s);
+                                dists, mflags, bb, s);
     case 2:
       return plain_batch_cfg<2>(cfg, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
-                                dists, bb, s);
+                                dists, mflags, bb, s);
     default:
       return -2;
   }

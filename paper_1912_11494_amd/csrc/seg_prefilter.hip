@@ -166,6 +166,7 @@ struct PfJob {
   const int32_t* bid;
   int32_t* labels;
   float* dists;
+  Metric mt;
 };
 
 // Centroid tiles per LDS chunk for a feature width.
@@ -346,7 +347,7 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
           }
         } else {
           if (qn > (uint32_t)(QCAP - 64)) {
-            queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
+            queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc, job.mt);
             qn = 0;
           }
           queue_push(wq, qn, msk, (cent << 8) | (uint32_t)slot);
@@ -402,10 +403,10 @@ __device__ __forceinline__ void prefilter_block(const PfJob& job, int64_t block,
     extract_tile(tile);
   }
   if (PAIRS) return;
-  queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc);
+  queue_drain_call<STATS>(wq, qn, fib_base, cprep, sc, job.mt);
   for (int k = lane; k < FPW; k += 64) {
     const int64_t f = wbase + k;
-    if (f < n) write_result(wq.keys[k], bid, labels + f, dists + f);
+    if (f < n) write_result(wq.keys[k], bid, labels + f, dists + f, job.mt.flags);
   }
 }
 
@@ -492,7 +493,7 @@ int resolve(int mode, int tile, Cfg* c) {
 template <int Q, int MAPK, int KP, int GF>
 int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, const int32_t* bid,
                int32_t* labels, float* dists, unsigned long long* counters, int32_t* pairs,
-               int64_t cap, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
+               int64_t cap, Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
   using MI = MapInfo<MAPK, KP>;
   constexpr int EB = QTraits<Q>::bytes;
   constexpr int FPB = 4 * GF * 32;  // fibers per block
@@ -517,7 +518,7 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
       cprep, m, ncols_pad, prm, cfeat, cb);
   const unsigned blocks = (unsigned)(n_pad / FPB);
   const PfJob job{(const uint8_t*)pb.fib_feat, pb.fib_h, cfeat, cb, ncols_pad, fibers, n, cprep,
-                  bid, labels, dists};
+                  bid, labels, dists, mt};
   if (pairs) {
     prefilter_kernel<Q, KP, GF, MI::CPC, false, true><<<blocks, 256, 0, s>>>(job, counters, pairs,
                                                                              cap);
@@ -536,11 +537,12 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
 
 int dispatch(const Cfg& c, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             int32_t* pairs, int64_t cap, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
+             int32_t* pairs, int64_t cap, Metric mt, PrefilterBuf& pb, hipEvent_t* ev,
+             hipStream_t s) {
 #define SEG_PF(QQ, MM, KK, GG)                                                                   \
   if (c.q == QQ && c.mapk == MM && c.kp == KK && c.gf == GG)                                     \
     return launch_cfg<QQ, MM, KK, GG>(fibers, n, cprep, m, bid, labels, dists, counters, pairs, \
-                                      cap, pb, ev, s);
+                                      cap, mt, pb, ev, s);
   SEG_PF(Q_BF16, MAP_SYM, 16, 2)
   SEG_PF(Q_BF16, MAP_SYM, 16, 4)
   SEG_PF(Q_BF16, MAP_SYM, 16, 1)
@@ -575,13 +577,14 @@ int dispatch(const Cfg& c, const float* fibers, int64_t n, const float* cprep, i
 template <int Q, int MAPK, int KP, int GF>
 int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* const* fibers,
               const int64_t* nf, int32_t ns, int32_t* const* labels, float* const* dists,
-              BatchBuf& bb, hipStream_t s) {
+              int mflags, BatchBuf& bb, hipStream_t s) {
   using MI = MapInfo<MAPK, KP>;
   constexpr int EB = QTraits<Q>::bytes;
   constexpr int FPB = 4 * GF * 32;
   constexpr int CC = 32 * Chunk<KP>::CH;
   constexpr size_t HDR = 512;  // PfParams at the head of the job buffer
-  std::vector<uint64_t> key = {2u, (uint64_t)mode, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns};
+  std::vector<uint64_t> key = {2u, (uint64_t)mode, (uint64_t)cfg, (uint64_t)na, (uint64_t)ns,
+                               (uint64_t)mflags};
   for (int32_t a = 0; a < na; ++a) {
     key.push_back((uint64_t)(uintptr_t)at[a].cprep);
     key.push_back((uint64_t)at[a].m);
@@ -635,7 +638,8 @@ int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* 
         jobs.push_back(PfJob{(const uint8_t*)bb.fib_feat + (size_t)foff[i] * KP * EB,
                              bb.fib_h + foff[i], cfeat + (size_t)coff[a] * KP * EB,
                              cbb + coff[a], ncp[a], fibers[i], nf[i], at[a].cprep, at[a].bid,
-                             labels[i * na + a], dists[i * na + a]});
+                             labels[i * na + a], dists[i * na + a],
+                             Metric{at[a].cext, mflags}});
         start.push_back(start.back() + npad[i] / FPB);
       }
     }
@@ -691,10 +695,12 @@ int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* 
 
 int batch_dispatch(int mode, int cfg, const Cfg& c, const BatchAtlas* at, int32_t na,
                    const float* const* fibers, const int64_t* nf, int32_t ns,
-                   int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s) {
+                   int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
+                   hipStream_t s) {
 #define SEG_PFB(QQ, MM, KK, GG)                                                             \
   if (c.q == QQ && c.mapk == MM && c.kp == KK && c.gf == GG)                                \
-    return batch_cfg<QQ, MM, KK, GG>(mode, cfg, at, na, fibers, nf, ns, labels, dists, bb, s);
+    return batch_cfg<QQ, MM, KK, GG>(mode, cfg, at, na, fibers, nf, ns, labels, dists, mflags, \
+                                     bb, s);
   SEG_PFB(Q_BF16, MAP_SYM, 16, 2)
   SEG_PFB(Q_BF16, MAP_SYM, 16, 1)
   SEG_PFB(Q_BF16, MAP_SYM, 32, 2)
@@ -711,11 +717,12 @@ int batch_dispatch(int mode, int cfg, const Cfg& c, const BatchAtlas* at, int32_
 
 int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
                     const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
-                    int32_t* const* labels, float* const* dists, BatchBuf& bb, hipStream_t s) {
+                    int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
+                    hipStream_t s) {
   Cfg c;
   if (resolve(mode, cfg, &c)) return -2;
   return batch_dispatch(mode, cfg, c, atlases, n_atlases, fibers, n_fibers, n_subjects, labels,
-                        dists, bb, s);
+                        dists, mflags, bb, s);
 }
 
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s) {
@@ -726,16 +733,17 @@ int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s)
 
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
-                  float* dists, unsigned long long* counters, PrefilterBuf& pb, hipEvent_t* ev,
-                  hipStream_t s) {
+                  float* dists, unsigned long long* counters, Metric mt, PrefilterBuf& pb,
+                  hipEvent_t* ev, hipStream_t s) {
   (void)ccen;
   // symmetric maps: the sorted, tile-culled form unless a streaming tile is
   // asked for (or the subject is too large for 32-bit sorted rows)
   if (mode >= 2 && mode <= 4 && (cfg == CULL_TILE || (cfg == 0 && n < ((int64_t)1 << 31))))
-    return run_cull(mode - 2, fibers, n, cprep, m, bid, labels, dists, counters, pb, ev, s);
+    return run_cull(mode - 2, fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
   Cfg c;
   if (resolve(mode, cfg, &c)) return -2;
-  return dispatch(c, fibers, n, cprep, m, bid, labels, dists, counters, nullptr, 0, pb, ev, s);
+  return dispatch(c, fibers, n, cprep, m, bid, labels, dists, counters, nullptr, 0, mt, pb, ev,
+                  s);
 }
 
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
@@ -744,8 +752,8 @@ int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep
   (void)ccen;
   Cfg c;
   if (resolve(mode, 0, &c)) return -2;
-  return dispatch(c, fibers, n, cprep, m, nullptr, nullptr, nullptr, count, pairs, cap, pb,
-                  nullptr, s);
+  return dispatch(c, fibers, n, cprep, m, nullptr, nullptr, nullptr, count, pairs, cap,
+                  Metric{nullptr, 0}, pb, nullptr, s);
 }
 
 }  // namespace seg

@@ -49,7 +49,14 @@ class SegError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
-                ("profile_events", ctypes.c_void_p)]
+                ("profile_events", ctypes.c_void_p), ("metric", ctypes.c_int32)]
+
+
+# seg_metric flags (include/seg.h)
+METRIC_LENGTH_NORM = 1
+METRIC_DIRECTION = 2
+METRICS = {"": 0, "tn": METRIC_LENGTH_NORM, "dir": METRIC_DIRECTION,
+           "tn+dir": METRIC_LENGTH_NORM | METRIC_DIRECTION}
 
 
 class Stats(ctypes.Structure):
@@ -144,15 +151,26 @@ def _mode(mode) -> int:
     return int(mode)
 
 
-def options(mode="plain", validate=False, tile=0, stats=False, events=None) -> Options:
-    """seg_options; `events` is an optional address of two hipEvent_t."""
-    return Options(_mode(mode), int(bool(validate)), int(tile), int(bool(stats)), events)
+def _metric(metric) -> int:
+    if isinstance(metric, str):
+        if metric not in METRICS:
+            raise ValueError(f"unknown metric {metric!r}; one of {sorted(METRICS)}")
+        return METRICS[metric]
+    return int(metric)
+
+
+def options(mode="plain", validate=False, tile=0, stats=False, events=None,
+            metric=0) -> Options:
+    """seg_options; `events` is an optional address of two hipEvent_t; `metric`
+    is 0, an OR of METRIC_* flags, or one of "tn", "dir", "tn+dir"."""
+    return Options(_mode(mode), int(bool(validate)), int(tile), int(bool(stats)), events,
+                   _metric(metric))
 
 
 def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: torch.Tensor,
             bundle_thresholds: torch.Tensor, mode="plain", validate=False, tile=0, stats=False,
             out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, stream=None,
-            events=None) -> Tuple[torch.Tensor, torch.Tensor]:
+            events=None, metric=0) -> Tuple[torch.Tensor, torch.Tensor]:
     """labels (int32 [N]) and dists (float32 [N]) of each fiber; see include/seg.h."""
     _dev(fibers, torch.float32, (21, 3), "fibers")
     _dev(centroids, torch.float32, (21, 3), "centroids")
@@ -166,7 +184,7 @@ def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: t
         labels, dists = out
         _dev(labels, torch.int32, None, "labels")
         _dev(dists, torch.float32, None, "dists")
-    opt = options(mode, validate, tile, stats, events)
+    opt = options(mode, validate, tile, stats, events, metric)
     rc = lib().seg_segment(fibers.data_ptr(), n, centroids.data_ptr(), centroids.shape[0],
                            centroid_bundle_id.data_ptr(), bundle_thresholds.data_ptr(),
                            bundle_thresholds.shape[0], labels.data_ptr(), dists.data_ptr(),
@@ -229,7 +247,7 @@ class Atlas:
             pass
 
     def segment(self, fibers, mode="plain", validate=False, tile=0, stats=False, stream=None,
-                events=None, out=None):
+                events=None, out=None, metric=0):
         _dev(fibers, torch.float32, (21, 3), "fibers")
         n = fibers.shape[0]
         if out is None:
@@ -237,7 +255,7 @@ class Atlas:
             dists = torch.empty(n, dtype=torch.float32, device=fibers.device)
         else:
             labels, dists = out
-        opt = options(mode, validate, tile, stats, events)
+        opt = options(mode, validate, tile, stats, events, metric)
         rc = lib().seg_segment_atlas(self.handle, fibers.data_ptr(), n, labels.data_ptr(),
                                      dists.data_ptr(), ctypes.byref(opt), _stream(stream))
         _check(rc)
@@ -245,7 +263,7 @@ class Atlas:
 
 
 def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mode="bf16",
-                  tile=0, outs=None, stream=None):
+                  tile=0, outs=None, stream=None, metric=0):
     """Labels/dists of every (subject, atlas) pair: a list over subjects of lists over atlases."""
     na, ns = len(atlases), len(subjects)
     for f in subjects:
@@ -260,7 +278,7 @@ def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mo
     nf = (ctypes.c_int64 * max(ns, 1))(*[f.shape[0] for f in subjects])
     lp = (P * max(ns * na, 1))(*[outs[s][a][0].data_ptr() for s in range(ns) for a in range(na)])
     dp = (P * max(ns * na, 1))(*[outs[s][a][1].data_ptr() for s in range(ns) for a in range(na)])
-    opt = options(mode, False, tile, False, None)
+    opt = options(mode, False, tile, False, None, metric)
     rc = lib().seg_segment_batch(ah, na, fp, nf, ns, lp, dp, ctypes.byref(opt), _stream(stream))
     _check(rc)
     return outs
