@@ -156,7 +156,7 @@ def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
     log(f"wrote {out_path}")
 
 
-def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
+def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     import torch
 
     stream = torch.cuda.current_stream()
@@ -165,7 +165,7 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
     out = (torch.empty(n, dtype=torch.int32, device=f.device),
            torch.empty(n, dtype=torch.float32, device=f.device))
     for _ in range(warmup):
-        P.segment(f, c, b, t, mode=mode, tile=tile, out=out)
+        P.segment(f, c, b, t, mode=mode, tile=tile, out=out, metric=metric)
     torch.cuda.synchronize()
     pairs = [(hip.event(), hip.event()) for _ in range(steps)]
     arrs = [(ctypes.c_void_p * 2)(a.value, z.value) for a, z in pairs]
@@ -174,7 +174,8 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0):
     h0 = time.perf_counter()
     hip.record(e0, sh)
     for k in range(steps):
-        P.segment(f, c, b, t, mode=mode, tile=tile, out=out, events=ctypes.addressof(arrs[k]))
+        P.segment(f, c, b, t, mode=mode, tile=tile, out=out, metric=metric,
+                  events=ctypes.addressof(arrs[k]))
     hip.record(e1, sh)
     torch.cuda.synchronize()
     h1 = time.perf_counter()
@@ -210,6 +211,9 @@ def main():
     ap.add_argument("--mode", default=None, help="headline mode (default: fastest built)")
     ap.add_argument("--compare", default="plain,dense,bf16,fp16,fp8,bf16_oriented,fp16:1,bf16:1",
                     help="modes to time, `mode` (library tile) or `mode:tile`")
+    ap.add_argument("--variants", default="tn,dir,tn+dir",
+                    help="metric variants timed on the headline mode (Eq. 3 length "
+                         "normalisation `tn`, section 2.4 direction inference `dir`)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="fibers of the workload the CPU oracle is timed on (0: all)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -335,6 +339,21 @@ def main():
                                          "frac": a_d / PEAK_FP32, "kernel_ms": dm["kernel_ms"],
                                          "traffic": traffic_for("dense_kernel")}
 
+    # metric variants on the headline form: same path, variant decision in the exact stage
+    variants = {}
+    hmode, _, htile = head.partition(":")
+    for v in [x for x in args.variants.split(",") if x]:
+        rv, out = time_mode(P, hip, f, c, b, t, hmode, args.steps, args.warmup, int(htile or 0),
+                            metric=v)
+        lv, dv = out[0].cpu().numpy(), out[1].cpu().numpy()
+        variants[v] = {"ms_per_step": rv["ms_per_step"], "kernel_ms": rv["kernel_ms"],
+                       "pairs_per_s": N * M / (rv["ms_per_step"] * 1e-3),
+                       "vs_exact_ms": rv["ms_per_step"] / r["ms_per_step"],
+                       "labelled": int((lv >= 0).sum()),
+                       "label_diffs_vs_exact": int((lv != outs[head][0]).sum())}
+        log(f"variant {v} on {head}: {rv['ms_per_step']:.3f} ms/step, "
+            f"{variants[v]['label_diffs_vs_exact']} labels differ from Eq. 2")
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -378,6 +397,7 @@ def main():
         "modes": {m: {k: v for k, v in x.items() if k != "stats"} | {"stats": x["stats"]}
                   for m, x in modes.items()},
         "roofline": roofline,
+        "variants": variants,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }

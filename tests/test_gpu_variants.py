@@ -157,3 +157,31 @@ def test_unknown_metric_rejected(seg):
     with pytest.raises(seg.SegError) as e:
         seg.segment(f, c, b, t, metric=4)
     assert e.value.code == -1
+
+
+def test_variants_full_size_sampled(seg):
+    """Paper-scale subject (4.1M x 10k) in the benchmark's launch configuration
+    for each variant; the oracle recomputes a fixed sample of fibers."""
+    import torch
+
+    wl = "paper-4145k-x-10k"
+    at = synth.workload_atlases(wl)[0]
+    subj = synth.workload_subjects(wl)[0]
+    log(f"variants full size {wl}: generating {subj.n_fibers} fibers")
+    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=8)
+    f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(subj.n_fibers, 1500, replace=False))
+    idx = np.concatenate([idx, np.arange(subj.n_fibers - 100, subj.n_fibers)])
+    for metric, flags in METRICS.items():
+        want = oracle.segment_ext_f32(fib[idx], at.centroids, at.bundle_id, at.thresholds, flags)
+        for mode in ("plain", "fp16", "bf16"):
+            log(f"variants full size {metric} mode {mode}")
+            lab, dist = seg.segment(f, c, b, t, mode=mode, metric=metric)
+            torch.cuda.synchronize()
+            lab, dist = lab.cpu().numpy(), dist.cpu().numpy()
+            _assert_same(lab[idx], dist[idx], want, f"full {metric} {mode}")
+            ok = lab >= 0
+            assert ((lab >= -1) & (lab < at.n_bundles)).all()
+            assert (np.isfinite(dist) == ok).all()
+            assert (dist[ok] <= at.thresholds[lab[ok]]).all()
