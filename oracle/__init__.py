@@ -78,6 +78,8 @@ class Oracle:
         L.oracle_arc_length_f32.restype = ctypes.c_float
         L.oracle_tn_f32.argtypes = [ctypes.c_float, ctypes.c_float]
         L.oracle_tn_f32.restype = ctypes.c_float
+        L.oracle_resample_f32.argtypes = [P, P, i64, i64, ctypes.c_int, P]
+        L.oracle_resample_f32.restype = ctypes.c_int
         self.L = L
         self.path = path
 
@@ -129,6 +131,20 @@ class Oracle:
 
     def tn_f32(self, ls: float, lc: float) -> float:
         return float(self.L.oracle_tn_f32(ls, lc))
+
+    def resample_f32(self, points, offsets, threads: int = 0):
+        """Raw streamlines (points [P, 3] float32, CSR offsets [n + 1] int64)
+        to 21 points equidistant in arc length: float32 [n, 21, 3]."""
+        p, pp = _c(points, np.float32)
+        o, po = _c(offsets, np.int64)
+        if p.ndim != 2 or p.shape[1] != 3 or o.ndim != 1 or o.shape[0] < 1:
+            raise ValueError("points must be [P, 3] and offsets [n + 1]")
+        n = o.shape[0] - 1
+        out = np.empty((n, 21, 3), np.float32)
+        rc = self.L.oracle_resample_f32(pp, po, n, p.shape[0], threads, out.ctypes.data)
+        if rc:
+            raise ValueError(f"oracle_resample_f32 failed ({rc})")
+        return out
 
     def segment_f64(self, fibers, centroids, bid, thr, threads: int = 0):
         """float64 companion: (labels int32, dists float64, best centroid int32)."""
@@ -211,3 +227,7 @@ def accepted_pairs_f32(*a, **k):
 
 def segment_ext_f32(*a, **k):
     return get().segment_ext_f32(*a, **k)
+
+
+def resample_f32(*a, **k):
+    return get().resample_f32(*a, **k)

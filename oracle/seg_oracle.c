@@ -57,6 +57,25 @@
  *   dx * dx))) of p[i+1] - p[i], summed in point order; r = |lS - lC| / max
  *   (rounded once), u = r + 1, TN = u * u - 1 (each rounded); the complete
  *   metric sqrtf(D) + TN (rounded once).
+ * Resampling (oracle_resample_f32), the step before the comparison: every
+ *   subject fiber is brought to 21 points equidistant in arc length (section
+ *   2.3, classification algorithm; section 2.2: the atlas centroids carry 21
+ *   equidistant points).  A raw streamline is a polyline of P >= 1 points;
+ *   float32 readings:
+ *     segment length  g_j = sqrtf of the float32 squared length of
+ *                     d = fl(p_{j+1} - p_j), the same expression as the
+ *                     point distance (and the arc length above);
+ *     cumulative      s_0 = 0, s_{j+1} = fl(s_j + g_j), length L = s_{P-1};
+ *     targets         t_k = fl(fl(k * L) / 20), k = 1..19;
+ *     point k         on the first segment j with t_k <= s_{j+1}, at
+ *                     w = fl(fl(t_k - s_j) / g_j) clamped to [0, 1] (0 when
+ *                     g_j = 0): out = fmaf(w, fl(p_{j+1} - p_j), p_j) per
+ *                     coordinate; the last point if no segment qualifies
+ *                     (t_k above L by rounding);
+ *     end points      out_0 = p_0 and out_20 = p_{P-1}, copied;
+ *     one point       all 21 outputs are that point.
+ *   A streamline without points, or offsets outside [0, npts] or decreasing,
+ *   is an error.
  * Precisions:
  *   *_f32  the float32 decision above (labels must match it bit for bit);
  *   *_f64  the same definition in double precision with exact differences,
@@ -368,6 +387,68 @@ int oracle_segment_ext_f32(const float* fibers, int64_t n, const float* cen, int
   }
   free(lc);
   free(t2);
+  return 0;
+}
+
+/* ---------------------------------------------------------------- resampling */
+
+/* One streamline of P >= 1 points to 21 points; s is scratch of P floats. */
+static void resample_one_f32(const float* p, int64_t P, float* s, float* out) {
+  s[0] = 0.0f;
+  for (int64_t j = 0; j + 1 < P; ++j) {
+    float dx = p[3 * (j + 1)] - p[3 * j];
+    float dy = p[3 * (j + 1) + 1] - p[3 * j + 1];
+    float dz = p[3 * (j + 1) + 2] - p[3 * j + 2];
+    s[j + 1] = s[j] + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
+  float L = s[P - 1];
+  for (int c = 0; c < 3; ++c) {
+    out[c] = p[c];
+    out[3 * (NP - 1) + c] = p[3 * (P - 1) + c];
+  }
+  for (int k = 1; k < NP - 1; ++k) {
+    float t = ((float)k * L) / 20.0f;
+    int64_t j = 0;
+    while (j + 1 < P && !(t <= s[j + 1])) ++j;
+    if (j + 1 >= P) {  /* no segment reaches t (or a single point) */
+      for (int c = 0; c < 3; ++c) out[3 * k + c] = p[3 * (P - 1) + c];
+      continue;
+    }
+    /* the segment's own length, not the difference of the rounded sums */
+    float dx = p[3 * (j + 1)] - p[3 * j];
+    float dy = p[3 * (j + 1) + 1] - p[3 * j + 1];
+    float dz = p[3 * (j + 1) + 2] - p[3 * j + 2];
+    float g = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    float w = g > 0.0f ? (t - s[j]) / g : 0.0f;
+    w = w < 0.0f ? 0.0f : (w > 1.0f ? 1.0f : w);
+    for (int c = 0; c < 3; ++c) {
+      float a = p[3 * j + c], b = p[3 * (j + 1) + c];
+      out[3 * k + c] = fmaf(w, b - a, a);
+    }
+  }
+}
+
+int oracle_resample_f32(const float* pts, const int64_t* off, int64_t n, int64_t npts,
+                        int nthreads, float* out) {
+  if (n < 0 || npts < 0) return -1;
+  int64_t pmax = 1;
+  for (int64_t i = 0; i < n; ++i) {
+    if (off[i] < 0 || off[i + 1] > npts || off[i + 1] <= off[i]) return -2;
+    if (off[i + 1] - off[i] > pmax) pmax = off[i + 1] - off[i];
+  }
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    float* s = (float*)malloc((size_t)pmax * sizeof(float));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i)
+      resample_one_f32(pts + 3 * off[i], off[i + 1] - off[i], s, out + (size_t)i * 3 * NP);
+    free(s);
+  }
   return 0;
 }
 

@@ -12,6 +12,7 @@ from .fibers import (  # noqa: F401
     bezier_curves,
     make_atlas,
     make_fibers,
+    raw_streamlines,
     workload_atlases,
     workload_subjects,
     workload_seed,

@@ -8,15 +8,15 @@ section 2.1-2.2) is not available, so these curves stand in for it.
 
 Recipe (one reading of the workload text, fixed here once):
 
-* A centroid is a cubic Bezier curve.  Its target length L is uniform in
-  [len_lo, len_hi].  The control points P1..P3 are P0 plus offsets uniform in a
-  cube of side 0.6 L.  The curve is sampled at ``_SAMPLES`` parameter values
-  and scaled about P0 so that the sampled polyline has arc length L.  It is
-  then resampled to 21 points equidistant in arc length; a shape whose
-  resampled chord spacing varies by more than 25% (a cusp) is redrawn.  P0 is
-  drawn uniformly
-  among the positions that keep the whole curve inside the 180 x 220 x 180 mm
-  box; a shape that cannot fit is redrawn.
+* A centroid follows the direction of a random cubic Bezier curve.  Its
+  length L is uniform in [len_lo, len_hi].  The control points P1..P3 are P0
+  plus offsets uniform in a cube of side 0.6 L.  Point i+1 is point i plus
+  L / 20 times the unit tangent of the Bezier curve at parameter
+  (i + 1/2) / 20, so the 21 points are equally spaced along the polyline by
+  construction (no resampling).  A shape that turns by more than 40 degrees
+  between two consecutive chords (near a cusp) is redrawn.  P0 is drawn
+  uniformly among the positions that keep the whole curve inside the
+  180 x 220 x 180 mm box; a shape that cannot fit is redrawn.
 * Centroids are stored bundle-major: centroid c belongs to bundle
   c // per_bundle.
 * Bundle thresholds are uniform in [thr_lo, thr_hi] (mm).
@@ -27,6 +27,12 @@ Recipe (one reading of the workload text, fixed here once):
 * An unmatched fiber is an independent curve from the centroid generator.
 * Fibers are generated in chunks of ``CHUNK`` with an independent random
   stream per chunk, so any fiber range can be generated without the rest.
+* A raw streamline (the tractography output before resampling) is a 21-point
+  fiber densified by its parameter: m = max(1, round(|p1 - p0| / step)) points
+  per chord, 20 m + 1 in all, placed by linear interpolation at parameter
+  j / m, interior points moved by N(0, jitter^2 I3); with probability ``dup``
+  one interior point is repeated (a zero-length step).  The step defaults to
+  the paper's 0.2 mm tractography step.
 
 Nothing here evaluates a fiber-to-centroid distance.
 """
@@ -40,7 +46,7 @@ import numpy as np
 N_POINTS = 21
 BOX = np.array([180.0, 220.0, 180.0])
 CHUNK = 65536
-_SAMPLES = 48
+_MAX_TURN_DEG = 40.0
 
 
 @dataclass(frozen=True)
@@ -133,68 +139,65 @@ def _rng(*key: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(key))))
 
 
-def _bernstein(samples: int) -> np.ndarray:
-    t = np.linspace(0.0, 1.0, samples)
-    return np.stack([(1 - t) ** 3, 3 * t * (1 - t) ** 2, 3 * t**2 * (1 - t), t**3], 0)
-
-
-def _resample_equidistant(poly: np.ndarray, n_out: int) -> np.ndarray:
-    """Points equidistant in arc length along each polyline (float64)."""
-    n, s, _ = poly.shape
-    seg = np.sqrt((np.diff(poly, axis=1) ** 2).sum(2))  # [n, s-1]
-    cum = np.concatenate([np.zeros((n, 1)), np.cumsum(seg, 1)], 1)  # [n, s]
-    total = cum[:, -1]
-    tgt = np.linspace(0.0, 1.0, n_out)[None, :] * total[:, None]  # [n, n_out]
-    stride = float(total.max()) * 2.0 + 1.0
-    off = np.arange(n, dtype=np.float64)[:, None] * stride
-    j = np.searchsorted((cum + off).ravel(), (tgt + off).ravel(), side="right") - 1
-    j = j.reshape(n, n_out) - np.arange(n)[:, None] * s
-    j = np.clip(j, 0, s - 2)
-    rows = np.arange(n)[:, None]
-    c0 = cum[rows, j]
-    seglen = seg[rows, j]
-    w = np.where(seglen > 0, (tgt - c0) / np.where(seglen > 0, seglen, 1.0), 0.0)
-    w = np.clip(w, 0.0, 1.0)[..., None]
-    out = poly[rows, j] * (1 - w) + poly[rows, j + 1] * w
-    out[:, 0] = poly[:, 0]
-    out[:, -1] = poly[:, -1]
-    return out
-
-
 def bezier_curves(rng: np.random.Generator, n: int, len_lo: float, len_hi: float,
-                  box: np.ndarray = BOX, samples: int = _SAMPLES) -> np.ndarray:
-    """``n`` random cubic Bezier curves resampled to 21 points, float64 [n,21,3]."""
+                  box: np.ndarray = BOX) -> np.ndarray:
+    """``n`` random smooth curves of 21 equally spaced points, float64 [n,21,3]."""
     out = np.empty((n, N_POINTS, 3))
     todo = np.arange(n)
-    bern = _bernstein(samples)  # [4, S]
+    t = (np.arange(N_POINTS - 1) + 0.5) / (N_POINTS - 1)
+    dbasis = np.stack([(1 - t) ** 2, 2 * t * (1 - t), t**2], 0)  # [3, 20]
+    cos_max = np.cos(np.deg2rad(_MAX_TURN_DEG))
     while todo.size:
         k = todo.size
         length = rng.uniform(len_lo, len_hi, k)
         side = 0.6 * length
         ctrl = np.zeros((k, 4, 3))
         ctrl[:, 1:, :] = rng.uniform(-0.5, 0.5, (k, 3, 3)) * side[:, None, None]
-        poly = (ctrl.transpose(0, 2, 1).reshape(-1, 4) @ bern).reshape(k, 3, samples)
-        poly = poly.transpose(0, 2, 1)  # [k, S, 3], P0 at the origin
-        arc = np.sqrt((np.diff(poly, axis=1) ** 2).sum(2)).sum(1)
-        ok = arc > 1e-6 * length
-        scale = np.where(ok, length / np.where(ok, arc, 1.0), 0.0)
-        poly *= scale[:, None, None]
-        lo = poly.min(1)
-        hi = poly.max(1)
+        diff = ctrl[:, 1:, :] - ctrl[:, :-1, :]  # [k, 3, 3]
+        tan = np.einsum("kjc,jt->ktc", diff, dbasis)  # [k, 20, 3], Bezier tangent / 3
+        speed = np.sqrt((tan**2).sum(2))
+        ok = speed.min(1) > 1e-6 * length
+        u = tan / np.where(speed > 0, speed, 1.0)[..., None]
+        turn = (u[:, 1:] * u[:, :-1]).sum(2).min(1)
+        ok &= turn >= cos_max
+        pts = np.zeros((k, N_POINTS, 3))
+        pts[:, 1:] = np.cumsum(u * (length / (N_POINTS - 1))[:, None, None], 1)
+        lo = pts.min(1)
+        hi = pts.max(1)
         fits = ok & np.all(hi - lo <= box[None, :], axis=1)
-        pts = _resample_equidistant(poly[fits], N_POINTS)
-        # streamlines are smooth: a shape with a cusp (chord spacing of the
-        # resampled points varying by more than 25%) is redrawn
-        chord = np.sqrt((np.diff(pts, axis=1) ** 2).sum(2))
-        smooth = chord.max(1) <= 1.25 * chord.min(1)
-        idx = np.nonzero(fits)[0]
-        fits[idx[~smooth]] = False
-        pts = pts[smooth]
         p0 = lo[fits] * -1.0 + rng.uniform(0.0, 1.0, (int(fits.sum()), 3)) * (
             box[None, :] - (hi[fits] - lo[fits]))
-        out[todo[fits]] = pts + p0[:, None, :]
+        out[todo[fits]] = pts[fits] + p0[:, None, :]
         todo = todo[~fits]
     return out
+
+
+def raw_streamlines(fibers: np.ndarray, rng: np.random.Generator, step: float = 0.2,
+                    jitter: float = 0.02, dup: float = 0.01):
+    """Raw streamlines drawn around 21-point fibers (see the recipe above):
+    (points float32 [P, 3], offsets int64 [n + 1])."""
+    f = np.asarray(fibers, np.float64)
+    n = f.shape[0]
+    chord = np.sqrt(((f[:, 1] - f[:, 0]) ** 2).sum(1)) if n else np.zeros(0)
+    m = np.maximum(1, np.rint(chord / step)).astype(np.int64)
+    base_k = (N_POINTS - 1) * m + 1
+    extra = (rng.random(n) < dup) & (base_k > 2)
+    dpos = np.minimum(rng.integers(1, np.maximum(base_k - 1, 2)), base_k - 2)
+    k = base_k + extra
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(k, out=off[1:])
+    fid = np.repeat(np.arange(n), k)
+    j = np.arange(off[-1]) - off[fid]
+    j = j - (extra[fid] & (j > dpos[fid]))  # the repeated point reuses index dpos
+    u = j / m[fid]
+    i0 = np.minimum(np.floor(u).astype(np.int64), N_POINTS - 2)
+    w = (u - i0)[:, None]
+    pts = f[fid, i0] * (1 - w) + f[fid, i0 + 1] * w
+    noise = rng.normal(0.0, jitter, (off[-1], 3))
+    # the same displacement for a point and its repeat; none on the end points
+    interior = (j > 0) & (j < base_k[fid] - 1)
+    pts[interior] += noise[(off[fid] + j)[interior]]
+    return pts.astype(np.float32), off
 
 
 def make_atlas(spec: AtlasSpec, seed: int) -> Atlas:

@@ -1,4 +1,4 @@
-"""Write the small seeded golden case: inputs from ``synth``, outputs from ``oracle``.
+"""Write the small seeded golden cases: inputs from ``synth``, outputs from ``oracle``.
 
 Run from the repository root:  python tests/golden/make_golden.py
 """
@@ -15,6 +15,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "small_seeded_case.json")
+OUT_RS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "small_resample_case.json")
 
 
 def main():
@@ -41,6 +42,26 @@ def main():
     with open(OUT, "w") as fh:
         json.dump(doc, fh)
     print(OUT, int((lab >= 0).sum()), "labelled")
+
+    # raw streamlines around 8 of those fibers (1 mm steps), plus a single
+    # point and a two-point streamline
+    rng = np.random.default_rng(20191225)
+    pts, off = synth.raw_streamlines(fib[:8], rng, step=1.0, jitter=0.02, dup=0.3)
+    pts = np.concatenate([pts, fib[12, :1], fib[13, [0, 20]]])
+    off = np.concatenate([off, [off[-1] + 1, off[-1] + 3]])
+    rs = oracle.resample_f32(pts, off)
+    doc = {
+        "about": "10 raw streamlines (8 densified fibers of the seeded case with 1 mm "
+                 "steps and repeated points, one single point, one two-point line); "
+                 "expected 21-point resampling written by the CPU oracle (float32, points "
+                 "equidistant in arc length, section 2.3).",
+        "points": [float(x) for x in pts.ravel()],
+        "offsets": [int(x) for x in off],
+        "resampled": [float(x) for x in rs.ravel()],
+    }
+    with open(OUT_RS, "w") as fh:
+        json.dump(doc, fh)
+    print(OUT_RS, len(off) - 1, "streamlines,", pts.shape[0], "points")
 
 
 if __name__ == "__main__":

@@ -464,6 +464,140 @@ def pin_dir_consistent_copies(O, seed=14):
     assert all(np.array_equal(x, y) for x, y in zip(e, d))
 
 
+# ---------------------------------------------------------------- resampling
+
+def _csr(lines):
+    """Stack polylines into (points [P, 3] float32, offsets [n + 1] int64)."""
+    off = np.zeros(len(lines) + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in lines])
+    pts = np.concatenate([np.asarray(x, F32).reshape(-1, 3) for x in lines]) if lines else \
+        np.zeros((0, 3), F32)
+    return pts, off
+
+
+def _raw_curve(rng, npts, length, start):
+    """A smooth bent curve sampled at ``npts`` random, unevenly spaced parameters."""
+    t = np.sort(rng.uniform(0, 1, npts))
+    t[0], t[-1] = 0.0, 1.0
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    v = rng.normal(size=3)
+    v -= v.dot(u) * u
+    v /= np.linalg.norm(v)
+    pts = np.asarray(start)[None, :] + length * t[:, None] * u[None, :] \
+        + 0.2 * length * np.sin(np.pi * t)[:, None] * v[None, :]
+    return pts.astype(F32)
+
+
+def _interp_f64(p):
+    """21 points equidistant in arc length by np.interp over the float64
+    cumulative length (a library routine, not the oracle's loop)."""
+    q = p.astype(np.float64)
+    cum = np.concatenate([[0.0], np.cumsum(np.sqrt((np.diff(q, axis=0) ** 2).sum(1)))])
+    t = np.linspace(0.0, cum[-1], 21)
+    return np.stack([np.interp(t, cum, q[:, c]) for c in range(3)], 1)
+
+
+def pin_resample_closed_forms(O):
+    """Straight lines with exact spacings: 41 points j (1.5, 2, 0) give k (3, 4, 0);
+    two points give p0 + k/20 (p1 - p0); 21 unit steps give the input back; one
+    point or a zero-length line gives 21 copies; end points are copied."""
+    base = np.array([64.0, 32.0, 16.0])
+    line = base + np.arange(41)[:, None] * np.array([1.5, 2.0, 0.0])
+    two = np.array([[10.0, 20.0, 30.0], [30.0, 60.0, 90.0]])
+    steps = [np.array([1.0, 0, 0]), np.array([0, 1.0, 0]), np.array([0, 0, -1.0])]
+    walk = np.zeros((21, 3))
+    walk[0] = base
+    for i in range(1, 21):
+        walk[i] = walk[i - 1] + steps[i % 3]
+    single = np.array([[5.0, 6.0, 7.0]])
+    still = np.repeat(np.array([[1.0, 2.0, 3.0]]), 7, 0)
+    out = O.resample_f32(*_csr([line, two, walk, single, still]))
+    k = np.arange(21)[:, None]
+    assert np.array_equal(out[0], (base + k * np.array([3.0, 4.0, 0.0])).astype(F32))
+    want2 = two[0] + k / 20.0 * (two[1] - two[0])
+    assert np.abs(out[1] - want2).max() <= 4 * 2.0**-24 * 90.0
+    assert np.array_equal(out[1][[0, 20]], two.astype(F32))
+    assert np.array_equal(out[2], walk.astype(F32))
+    assert np.array_equal(out[3], np.repeat(single, 21, 0).astype(F32))
+    assert np.array_equal(out[4], np.repeat(still[:1], 21, 0).astype(F32))
+
+
+def pin_resample_uneven_line(O, seed=15):
+    """A straight line with uneven spacing (coordinates on a 1/64 grid, so the
+    arc length sums are exact): point k sits at arc length k L / 20, not at
+    an index fraction."""
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        x = np.unique(np.round(rng.uniform(0, 40, 30) * 64) / 64)
+        x = np.concatenate([[0.0], x[(x > 0) & (x < 40)], [40.0]])
+        p = np.zeros((x.size, 3))
+        p[:, 0] = 50.0 + x
+        p[:, 1] = 70.0
+        p[:, 2] = 90.0
+        out = O.resample_f32(*_csr([p]))[0]
+        want = 50.0 + 2.0 * np.arange(21)
+        assert np.abs(out[:, 0] - want).max() <= 2.0**-24 * 90.0 * 2
+        assert (out[:, 1] == 70.0).all() and (out[:, 2] == 90.0).all()
+
+
+def pin_resample_vs_interp(O, seed=16):
+    """Smooth curves sampled unevenly (2 to 600 points) agree with np.interp over
+    the float64 arc length within the float32 error of P sequential sums."""
+    rng = np.random.default_rng(seed)
+    lines = [_raw_curve(rng, int(rng.integers(2, 600)), rng.uniform(5, 200),
+                        rng.uniform([20, 20, 20], [150, 190, 150])) for _ in range(60)]
+    out = O.resample_f32(*_csr(lines))
+    for p, o in zip(lines, out):
+        want = _interp_f64(p)
+        L = float(np.sqrt((np.diff(p.astype(np.float64), axis=0) ** 2).sum(1)).sum())
+        tol = 2.0 * (len(p) + 4) * 2.0**-24 * L + 1e-5
+        assert np.abs(o - want).max() <= tol, (len(p), np.abs(o - want).max(), tol)
+        assert np.array_equal(o[[0, 20]], p[[0, -1]])
+
+
+def pin_resample_invariants(O, seed=17):
+    """Repeating points (zero-length steps) changes nothing, bit for bit; a set
+    gives each streamline's own result; reversal gives the reversed points
+    within the float32 error; bad offsets are rejected."""
+    rng = np.random.default_rng(seed)
+    lines = [_raw_curve(rng, int(rng.integers(3, 300)), rng.uniform(10, 150),
+                        rng.uniform([20, 20, 20], [150, 190, 150])) for _ in range(20)]
+    whole = O.resample_f32(*_csr(lines))
+    for i, p in enumerate(lines):
+        assert np.array_equal(O.resample_f32(*_csr([p]))[0], whole[i])
+        rep = np.repeat(p, rng.integers(1, 3, len(p)), axis=0)
+        assert np.array_equal(O.resample_f32(*_csr([rep]))[0], whole[i])
+        rev = O.resample_f32(*_csr([p[::-1]]))[0]
+        L = float(np.sqrt((np.diff(p.astype(np.float64), axis=0) ** 2).sum(1)).sum())
+        assert np.abs(rev[::-1] - whole[i]).max() <= 4.0 * (len(p) + 4) * 2.0**-24 * L + 1e-5
+    pts, off = _csr(lines[:3])
+    for bad in ([0, 5, 5, off[3]], [0, 5, 3, off[3]], [0, 5, 9, off[3] + 1], [-1, 5, 9, off[3]]):
+        try:
+            O.resample_f32(pts, np.array(bad, np.int64))
+        except ValueError:
+            continue
+        raise AssertionError(f"offsets {bad} accepted")
+
+
+def pin_resample_rounding_corners(O):
+    """Two float32 corners, worked by hand from the stated reading.
+    (a) Along x: 0, 2^25, 1, 2^26.  fl(1 - 2^25) = -2^25 (a tie, to even), so the
+        lengths are 2^25, 2^25, 2^26, L = 2^27 and t_10 = 2^26 = s_2: the first
+        segment reaching t_10 is the second, at w = 1, and fl(2^25 + fl(1 - 2^25))
+        puts point 10 at x = 0, not at the third input point (x = 1).
+    (b) (0,0,0), (2^24,0,0), (2^24,1.5,0), (2^24,1.5,2^24+2): lengths 2^24, 1.5,
+        2^24+2; s_2 = fl(2^24 + 1.5) = 2^24 + 2, L = 2^25 + 4, t_10 = 2^24 + 2
+        (fl(10 L) = 335544352), so w = 2 / 1.5 is clamped to 1: point 10 is the
+        third input point; t_5 = 8388609 gives (8388609, 0, 0)."""
+    a = np.array([[0.0, 0, 0], [2.0**25, 0, 0], [1.0, 0, 0], [2.0**26, 0, 0]])
+    b = np.array([[0.0, 0, 0], [2.0**24, 0, 0], [2.0**24, 1.5, 0], [2.0**24, 1.5, 2.0**24 + 2]])
+    out = O.resample_f32(*_csr([a, b]))
+    assert np.array_equal(out[0][10], np.array([0.0, 0.0, 0.0], F32)), out[0][10]
+    assert np.array_equal(out[1][10], b[2].astype(F32)), out[1][10]
+    assert np.array_equal(out[1][5], np.array([8388609.0, 0.0, 0.0], F32)), out[1][5]
+
+
 ALL_PINS = [
     pin_expression_rounding,
     pin_straight_translation,
@@ -484,4 +618,9 @@ ALL_PINS = [
     pin_dir_closed_form,
     pin_dir_tie_direct,
     pin_dir_consistent_copies,
+    pin_resample_closed_forms,
+    pin_resample_uneven_line,
+    pin_resample_vs_interp,
+    pin_resample_invariants,
+    pin_resample_rounding_corners,
 ]

@@ -1,4 +1,4 @@
-"""The oracle reproduces the stored seeded case (guards the oracle against drift)."""
+"""The oracle reproduces the stored seeded cases (guards the oracle against drift)."""
 import json
 import os
 
@@ -27,3 +27,19 @@ def test_golden_oracle(O):
     assert l64.tolist() == d["labels_f64"]
     assert np.array_equal(d64, np.array(d["dists_f64"]))
     assert 20 <= (lab >= 0).sum() < len(lab)
+
+
+PATH_RS = os.path.join(os.path.dirname(__file__), "golden", "small_resample_case.json")
+
+
+def load_resample():
+    with open(PATH_RS) as fh:
+        d = json.load(fh)
+    return (np.array(d["points"], np.float32).reshape(-1, 3), np.array(d["offsets"], np.int64),
+            np.array(d["resampled"], np.float32).reshape(-1, 21, 3))
+
+
+def test_golden_resample(O):
+    pts, off, want = load_resample()
+    assert np.array_equal(O.resample_f32(pts, off), want)
+    assert len(off) == 11 and np.diff(off).min() == 1

@@ -52,6 +52,18 @@ MUTANTS = {
     "dir_picks_larger": ("int direct = ed <= ei;\n  float mx = direct ? ed : ei;", "int direct = ed > ei;\n  float mx = direct ? ed : ei;"),
     "dir_ignored_brute": ("if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);",
                           "if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);"),
+    "resample_k_over_21": ("float t = ((float)k * L) / 20.0f;", "float t = ((float)k * L) / 21.0f;"),
+    "resample_strict_tie": ("while (j + 1 < P && !(t <= s[j + 1])) ++j;",
+                            "while (j + 1 < P && !(t < s[j + 1])) ++j;"),
+    "resample_no_clamp": ("w = w < 0.0f ? 0.0f : (w > 1.0f ? 1.0f : w);", "w = w < 0.0f ? 0.0f : w;"),
+    "resample_from_far_end": ("out[3 * k + c] = fmaf(w, b - a, a);", "out[3 * k + c] = fmaf(w, a - b, b);"),
+    "resample_by_index": ("s[j + 1] = s[j] + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));",
+                          "s[j + 1] = s[j] + 1.0f;"),
+    "resample_last_point_off_by_one": ("out[3 * (NP - 1) + c] = p[3 * (P - 1) + c];",
+                                       "out[3 * (NP - 1) + c] = p[3 * (P > 1 ? P - 2 : 0) + c];"),
+    "resample_skips_first_segment": ("for (int64_t j = 0; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];",
+                                     "s[1] = 0.0f;\n  for (int64_t j = 1; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];"),
+    "resample_accepts_empty": ("off[i + 1] <= off[i]) return -2;", "off[i + 1] < off[i]) return -2;"),
 }
 
 

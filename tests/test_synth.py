@@ -52,3 +52,33 @@ def test_matched_fraction():
     rev = (fib[:, ::-1].reshape(2000, 1, -1) == cen[None]).all(2).any(1)
     assert (fwd | rev).sum() == 1000
     assert 400 < rev.sum() < 600
+
+
+def test_centroids_equal_chords_by_construction():
+    at = synth.make_atlas(synth.AtlasSpec(5, 40, 20.0, 80.0, 5.0, 8.0), 4)
+    c = at.centroids.astype(np.float64)
+    chord = np.linalg.norm(np.diff(c, axis=1), axis=2)
+    assert (chord.max(1) / chord.min(1) < 1 + 1e-4).all()
+    u = np.diff(c, axis=1) / chord[..., None]
+    turn = np.degrees(np.arccos(np.clip((u[:, 1:] * u[:, :-1]).sum(2), -1, 1)))
+    assert turn.max() <= 40.0 + 1e-2
+
+
+def test_raw_streamlines_shape():
+    fib, _ = synth.small_case(300, 3, 5, seed=8, len_lo=20.0, len_hi=80.0)
+    rng = np.random.default_rng(3)
+    pts, off = synth.raw_streamlines(fib, rng, step=0.2, jitter=0.0, dup=0.5)
+    assert pts.dtype == np.float32 and off.dtype == np.int64 and off[0] == 0
+    assert off[-1] == pts.shape[0] and len(off) == 301
+    for i in range(0, 300, 37):
+        p = pts[off[i]:off[i + 1]].astype(np.float64)
+        assert np.array_equal(p[0], fib[i, 0]) and np.array_equal(p[-1], fib[i, 20])
+        step = np.linalg.norm(np.diff(p, axis=0), axis=1)
+        assert np.median(step) < 0.3 and step.max() < 0.5
+    # about half the streamlines repeat one point (a zero-length step)
+    zero = [(np.linalg.norm(np.diff(pts[off[i]:off[i + 1]], axis=0), axis=1) == 0).any()
+            for i in range(300)]
+    assert 100 < sum(zero) < 200
+    again, off2 = synth.raw_streamlines(fib, np.random.default_rng(3), step=0.2, jitter=0.0,
+                                        dup=0.5)
+    assert np.array_equal(again, pts) and np.array_equal(off2, off)
