@@ -48,12 +48,14 @@ TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf
                    ("seg::prefilter_kernel<1,", "prefilter_kernel:fp16"),
                    ("seg::prefilter_kernel<2,", "prefilter_kernel:fp8"),
                    ("seg::plain_kernel<", "plain_kernel"),
-                   ("seg::dense_kernel<1>", "dense_kernel")]
+                   ("seg::dense_kernel<1>", "dense_kernel"),
+                   ("seg::(anonymousnamespace)::resample_kernel", "resample_kernel")]
 KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
                   "paper_1912_11494_amd/csrc/seg_pf.hpp",
                   "paper_1912_11494_amd/csrc/seg_kernels.hip",
                   "paper_1912_11494_amd/csrc/seg_prefilter.hip",
-                  "paper_1912_11494_amd/csrc/seg_cull.hip"]
+                  "paper_1912_11494_amd/csrc/seg_cull.hip",
+                  "paper_1912_11494_amd/csrc/seg_resample.hip"]
 
 
 def log(msg):
@@ -190,6 +192,79 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     }, out
 
 
+def bench_resample(P, hip, f, at, c, b, t, wl, head, args, N, np):
+    """Raw streamlines of the workload's subject (0.2 mm steps, drawn on the
+    device) to 21 points: the resampling kernel alone, HIP events on its
+    stream, and resampling + segmentation in one library call."""
+    import torch
+
+    import synth
+
+    sh = torch.cuda.current_stream().cuda_stream
+    pts, off = synth.raw_streamlines_torch(f, synth.workload_seed(wl))
+    npts = pts.shape[0]
+    out = torch.empty((N, 21, 3), dtype=torch.float32, device=f.device)
+    for _ in range(args.warmup):
+        P.resample(pts, off, out=out)
+    torch.cuda.synchronize()
+    evs = [(hip.event(), hip.event()) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        hip.record(e0, sh)
+        P.resample(pts, off, out=out)
+        hip.record(e1, sh)
+    torch.cuda.synchronize()
+    kern = [hip.elapsed(e0, e1) for e0, e1 in evs]
+    ms = sum(kern) / len(kern)
+    alg_bytes = 12 * npts + 8 * (N + 1) + 4 * 63 * N
+    ach = alg_bytes / (ms * 1e-3) / 1e9
+    # raw streamlines to labels in one call (resample + the headline mode)
+    atlas = P.Atlas(c, b, t)
+    hmode, _, htile = head.partition(":")
+    lab = (torch.empty(N, dtype=torch.int32, device=f.device),
+           torch.empty(N, dtype=torch.float32, device=f.device))
+    for _ in range(args.warmup):
+        atlas.segment_streamlines(pts, off, mode=hmode, tile=int(htile or 0), fibers=out, out=lab)
+    torch.cuda.synchronize()
+    e0, e1 = hip.event(), hip.event()
+    hip.record(e0, sh)
+    for _ in range(args.steps):
+        atlas.segment_streamlines(pts, off, mode=hmode, tile=int(htile or 0), fibers=out, out=lab)
+    hip.record(e1, sh)
+    torch.cuda.synchronize()
+    e2e = hip.elapsed(e0, e1) / args.steps
+    res = {"ms": ms, "kernel_ms_min": min(kern), "kernel_ms_max": max(kern),
+           "streamlines": N, "points": npts, "streamlines_per_s": N / (ms * 1e-3),
+           "points_per_s": npts / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s",
+                        "frac": ach / PEAK_HBM, "traffic": traffic_for("resample_kernel"),
+                        "kernel": "resample_kernel", "alg_bytes": alg_bytes},
+           "resample_plus_segment_ms": e2e, "segment_mode": head}
+    log(f"resample: {npts} points in {ms:.3f} ms ({ach:.0f} GB/s algorithmic), "
+        f"with segmentation {e2e:.3f} ms")
+    if not args.no_cpu:
+        import oracle
+
+        # the oracle on the first streamlines (one contiguous slice of points)
+        ns = min(N, 200_000)
+        off_h = off[:ns + 1].cpu().numpy()
+        sp = pts[:int(off_h[-1])].cpu().numpy()
+        thr = oracle.get().max_threads()
+        h0 = time.perf_counter()
+        want = oracle.resample_f32(sp, off_h, threads=thr)
+        dt = time.perf_counter() - h0
+        got = out[:ns].cpu().numpy()
+        res["cpu_baseline"] = {"value": ns / dt, "unit": "streamlines/s", "cores": thr,
+                               "kind": "oracle",
+                               "sample": f"first {ns:,} of {N:,} streamlines "
+                                         f"({int(off_h[-1]):,} points), float32, OpenMP {thr} "
+                                         f"threads; {dt:.2f} s"}
+        res["sample_mismatches_vs_oracle"] = int((~((got == want) | (np.isnan(got) &
+                                                   np.isnan(want)))).any(axis=(1, 2)).sum())
+    del pts, off
+    atlas.close()
+    return res
+
+
 def alg_flops(mode, st, n, m, kfeat=None):
     """Algorithmic FLOPs of the dominant kernel per launch (8 FLOP per point
     distance: 3 sub, 3 mul, 2 add; 2 per multiply-add of the matrix product).
@@ -214,6 +289,8 @@ def main():
     ap.add_argument("--variants", default="tn,dir,tn+dir",
                     help="metric variants timed on the headline mode (Eq. 3 length "
                          "normalisation `tn`, section 2.4 direction inference `dir`)")
+    ap.add_argument("--no-resample", action="store_true",
+                    help="skip the resampling leg (raw streamlines to 21 points)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="fibers of the workload the CPU oracle is timed on (0: all)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -354,6 +431,9 @@ def main():
         log(f"variant {v} on {head}: {rv['ms_per_step']:.3f} ms/step, "
             f"{variants[v]['label_diffs_vs_exact']} labels differ from Eq. 2")
 
+    resample = None if args.no_resample else bench_resample(P, hip, f, at, c, b, t, wl, head,
+                                                            args, N, np)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -398,6 +478,7 @@ def main():
                   for m, x in modes.items()},
         "roofline": roofline,
         "variants": variants,
+        "resample": resample,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }

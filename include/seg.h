@@ -58,7 +58,8 @@ typedef enum seg_status {
   SEG_EHIP = -4,        /* a HIP runtime call failed */
   SEG_ENOMEM = -5,      /* scratch allocation failed */
   SEG_ERANGE = -6,      /* a size beyond what the kernels index (M >= 2^24) */
-  SEG_EMODE = -7        /* unknown mode or option value */
+  SEG_EMODE = -7,       /* unknown mode or option value */
+  SEG_EOFFSETS = -8     /* an empty streamline or offsets outside the points (validate = 1) */
 } seg_status;
 
 typedef enum seg_mode {
@@ -230,6 +231,46 @@ int seg_filter_pairs(const float* fibers, int64_t n_fibers, const float* centroi
                      int64_t n_centroids, const int32_t* centroid_bundle_id,
                      const float* bundle_thresholds, int32_t n_bundles, int32_t mode,
                      int32_t* pairs, int64_t capacity, int64_t* count, void* stream);
+
+/*
+ * Resampling of raw streamlines to 21 points equidistant in arc length: the
+ * step before the comparison (the paper resamples every subject fiber to 21
+ * equidistant points before classifying it, section 2.3; the atlas centroids
+ * carry 21 equidistant points, section 2.2).
+ *
+ * points   device, [n_points][3] float32 (x, y, z in mm), C-contiguous,
+ *          4-byte aligned.
+ * offsets  device, [n + 1] int64, 8-byte aligned: streamline i is
+ *          points[offsets[i]] .. points[offsets[i+1] - 1] (P_i >= 1 points).
+ * fibers   device output, [n][21][3] float32 (the fiber layout of
+ *          seg_segment), caller-owned.
+ *
+ * Arithmetic (float32, fixed so results are reproducible bit for bit):
+ *   segment j:  d = p[j+1] - p[j], g_j = sqrtf(fma(dz, dz, fma(dy, dy, dx*dx)));
+ *   s_0 = 0, s_{j+1} = s_j + g_j summed in point order, L = s_{P-1};
+ *   targets t_k = (k * L) / 20, k = 1..19, each rounded once;
+ *   point k lies on the first segment j with t_k <= s_{j+1}, at weight
+ *   w = (t_k - s_j) / g_j clamped to [0, 1] (0 when g_j = 0):
+ *   out_k = fma(w, d, p[j]) per coordinate; a target above every s (by
+ *   rounding) takes the last point; out_0 = p[0], out_20 = p[P-1] exactly;
+ *   a single point gives 21 copies of it.
+ * A streamline with no points, or whose offsets leave [0, n_points] or
+ * decrease, gets 21 NaN points and no read of `points`; with validate = 1
+ * the call synchronises the stream and returns SEG_EOFFSETS for it.
+ * n = 0 returns SEG_OK without launching.
+ */
+int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, int64_t n,
+                 float* fibers, int32_t validate, void* stream);
+
+/*
+ * Raw streamlines straight to labels: seg_resample into `fibers` (a
+ * caller-owned [n][21][3] float32 device buffer, which holds the resampled
+ * fibers afterwards), then seg_segment_atlas on them with `opt` (its
+ * validate field applies to both steps).
+ */
+int seg_segment_streamlines(const seg_atlas* atlas, const float* points, int64_t n_points,
+                            const int64_t* offsets, int64_t n, float* fibers, int32_t* labels,
+                            float* dists, const seg_options* opt, void* stream);
 
 /* Counters of the last call on this thread made with collect_stats = 1
    (synchronises that call's stream). */

@@ -410,6 +410,51 @@ int seg_segment_atlas(const seg_atlas* a, const float* fibers, int64_t n, int32_
   return run_mode(o, a->buf, sc, fibers, n, labels, dists, s);
 }
 
+int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, int64_t n,
+                 float* fibers, int32_t validate, void* stream) {
+  t_err.clear();
+  if (n < 0 || n_points < 0) return fail(SEG_EINVAL, "negative streamline or point count");
+  if (n == 0) return SEG_OK;
+  if (!offsets || !fibers || (n_points > 0 && !points))
+    return fail(SEG_EINVAL, "null points/offsets/fibers pointer");
+  if (!aligned4(points) || !aligned4(fibers) || ((uintptr_t)offsets & 7u))
+    return fail(SEG_EINVAL, "points/fibers must be 4-byte and offsets 8-byte aligned");
+  if (n_points > ((int64_t)1 << 60)) return fail(SEG_ERANGE, "n_points too large");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  int rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  unsigned int* flags = nullptr;
+  if (validate) {
+    if (seg::launch_fill_u64(sc->flags, 1, 0ull, s)) return hip_fail(hipGetLastError(), "flag reset");
+    flags = (unsigned int*)sc->flags;
+  }
+  if (seg::launch_resample(points, n_points, offsets, n, fibers, flags, s))
+    return hip_fail(hipGetLastError(), "resample launch");
+  if (validate) {
+    unsigned long long f = 0;
+    rc = read_flags(sc->flags, s, &f);
+    if (rc) return rc;
+    if (f & seg::FLAG_OFFSETS)
+      return fail(SEG_EOFFSETS, "a streamline is empty or its offsets leave [0, n_points]");
+  }
+  return SEG_OK;
+}
+
+int seg_segment_streamlines(const seg_atlas* a, const float* points, int64_t n_points,
+                            const int64_t* offsets, int64_t n, float* fibers, int32_t* labels,
+                            float* dists, const seg_options* opt, void* stream) {
+  t_err.clear();
+  if (!a) return fail(SEG_EINVAL, "null atlas");
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
+  if (rc) return rc;
+  rc = seg_resample(points, n_points, offsets, n, fibers, o.validate, stream);
+  if (rc) return rc;
+  return seg_segment_atlas(a, fibers, n, labels, dists, &o, stream);
+}
+
 int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const float* const* fibers,
                       const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
                       float* const* dists, const seg_options* opt, void* stream) {

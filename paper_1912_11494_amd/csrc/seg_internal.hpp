@@ -12,6 +12,7 @@ namespace seg {
 
 constexpr unsigned int FLAG_BUNDLE = 1u;
 constexpr unsigned int FLAG_NONFINITE = 2u;
+constexpr unsigned int FLAG_OFFSETS = 4u;
 
 // Number of 64-bit statistics counters (see StageCounts).
 constexpr int NCOUNTERS = 8;
@@ -76,6 +77,9 @@ int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const flo
                       int32_t nb, float* cprep, float4* ccen, int32_t* bid_out, float* cext,
                       unsigned int* flags, hipStream_t s);
 int launch_check_finite(const float* v, int64_t count, unsigned int* flags, hipStream_t s);
+// seg_resample.hip: raw streamlines (CSR) to [n][21][3]; flags may be null
+int launch_resample(const float* pts, int64_t npts, const int64_t* off, int64_t n, float* out,
+                    unsigned int* flags, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 int launch_fill_empty(int64_t n, int32_t* labels, float* dists, hipStream_t s);
 int launch_dense(const float* fibers, int64_t n, const float* cprep, int32_t m,

@@ -37,7 +37,8 @@ MODES = {
 }
 
 STATUS = {0: "SEG_OK", -1: "SEG_EINVAL", -2: "SEG_EBUNDLE", -3: "SEG_ENONFINITE",
-          -4: "SEG_EHIP", -5: "SEG_ENOMEM", -6: "SEG_ERANGE", -7: "SEG_EMODE"}
+          -4: "SEG_EHIP", -5: "SEG_ENOMEM", -6: "SEG_ERANGE", -7: "SEG_EMODE",
+          -8: "SEG_EOFFSETS"}
 
 
 class SegError(RuntimeError):
@@ -109,6 +110,11 @@ def lib():
         L.seg_tune_save.restype = ctypes.c_int
         L.seg_tune_load.argtypes = [ctypes.c_char_p]
         L.seg_tune_load.restype = ctypes.c_int
+        L.seg_resample.argtypes = [P, i64, P, i64, P, i32, P]
+        L.seg_resample.restype = ctypes.c_int
+        L.seg_segment_streamlines.argtypes = [P, P, i64, P, i64, P, P, P,
+                                              ctypes.POINTER(Options), P]
+        L.seg_segment_streamlines.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -217,6 +223,28 @@ def filter_pairs(fibers, centroids, centroid_bundle_id, bundle_thresholds, mode=
     return pairs[:cnt.value]
 
 
+def _streamlines(points, offsets):
+    _dev(points, torch.float32, (3,), "points")
+    _dev(offsets, torch.int64, None, "offsets")
+    if offsets.dim() != 1 or offsets.shape[0] < 1:
+        raise ValueError("offsets must be [n + 1]")
+    return offsets.shape[0] - 1
+
+
+def resample(points: torch.Tensor, offsets: torch.Tensor, out: Optional[torch.Tensor] = None,
+             validate=False, stream=None) -> torch.Tensor:
+    """Raw streamlines (points float32 [P, 3], CSR offsets int64 [n + 1]) to
+    21 points equidistant in arc length, float32 [n, 21, 3]; see include/seg.h."""
+    n = _streamlines(points, offsets)
+    if out is None:
+        out = torch.empty((n, 21, 3), dtype=torch.float32, device=points.device)
+    _dev(out, torch.float32, (21, 3), "out")
+    rc = lib().seg_resample(points.data_ptr(), points.shape[0], offsets.data_ptr(), n,
+                            out.data_ptr(), int(bool(validate)), _stream(stream))
+    _check(rc)
+    return out
+
+
 class Atlas:
     """A prepared atlas held by the library (seg_atlas_create / seg_atlas_destroy)."""
 
@@ -260,6 +288,27 @@ class Atlas:
                                      dists.data_ptr(), ctypes.byref(opt), _stream(stream))
         _check(rc)
         return labels, dists
+
+    def segment_streamlines(self, points, offsets, mode="plain", validate=False, tile=0,
+                            stats=False, stream=None, fibers=None, out=None, metric=0):
+        """Raw streamlines to (labels, dists, resampled fibers) in one library call."""
+        n = _streamlines(points, offsets)
+        dev = points.device
+        if fibers is None:
+            fibers = torch.empty((n, 21, 3), dtype=torch.float32, device=dev)
+        _dev(fibers, torch.float32, (21, 3), "fibers")
+        if out is None:
+            labels = torch.empty(n, dtype=torch.int32, device=dev)
+            dists = torch.empty(n, dtype=torch.float32, device=dev)
+        else:
+            labels, dists = out
+        opt = options(mode, validate, tile, stats, None, metric)
+        rc = lib().seg_segment_streamlines(self.handle, points.data_ptr(), points.shape[0],
+                                           offsets.data_ptr(), n, fibers.data_ptr(),
+                                           labels.data_ptr(), dists.data_ptr(), ctypes.byref(opt),
+                                           _stream(stream))
+        _check(rc)
+        return labels, dists, fibers
 
 
 def segment_batch(atlases: Sequence[Atlas], subjects: Sequence[torch.Tensor], mode="bf16",

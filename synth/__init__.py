@@ -13,6 +13,7 @@ from .fibers import (  # noqa: F401
     make_atlas,
     make_fibers,
     raw_streamlines,
+    raw_streamlines_torch,
     workload_atlases,
     workload_subjects,
     workload_seed,

@@ -200,6 +200,52 @@ def raw_streamlines(fibers: np.ndarray, rng: np.random.Generator, step: float = 
     return pts.astype(np.float32), off
 
 
+def raw_streamlines_torch(fibers, seed: int, step: float = 0.2, jitter: float = 0.02,
+                          dup: float = 0.01, chunk: int = 1 << 19):
+    """The raw-streamline recipe drawn with torch on the fibers' device (for
+    paper-scale subjects, ~10^9 points): (points float32 [P, 3], offsets int64
+    [n + 1]).  Same recipe as ``raw_streamlines``, a different random stream."""
+    import torch
+
+    dev = fibers.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    n = fibers.shape[0]
+    f = fibers.to(torch.float32)
+    chord = (f[:, 1] - f[:, 0]).double().pow(2).sum(1).sqrt()
+    m = torch.clamp(torch.round(chord / step), min=1).long()
+    base_k = (N_POINTS - 1) * m + 1
+    extra = (torch.rand(n, generator=g, device=dev) < dup).long()
+    dpos = 1 + (torch.rand(n, generator=g, device=dev, dtype=torch.float64)
+                * (base_k - 2).double()).long()
+    dpos = torch.minimum(dpos, base_k - 2)
+    k = base_k + extra
+    off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(k, 0, out=off[1:])
+    total = int(off[-1].item())
+    pts = torch.empty((total, 3), dtype=torch.float32, device=dev)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        p0, p1 = int(off[c0].item()), int(off[c1].item())
+        kk = k[c0:c1]
+        fid = torch.repeat_interleave(torch.arange(c0, c1, device=dev), kk, output_size=p1 - p0)
+        j = torch.arange(p0, p1, device=dev) - off[fid]
+        j = j - ((extra[fid] == 1) & (j > dpos[fid])).long()
+        u = j.double() / m[fid].double()
+        i0 = torch.clamp(torch.floor(u).long(), max=N_POINTS - 2)
+        w = (u - i0.double()).float()[:, None]
+        a = f[fid, i0]
+        b = f[fid, i0 + 1]
+        q = a * (1 - w) + b * w
+        noise = torch.randn((p1 - p0, 3), generator=g, device=dev) * jitter
+        # a repeated point takes the displacement of the point it repeats
+        src = j + off[fid] - p0
+        interior = (j > 0) & (j < base_k[fid] - 1)
+        q = torch.where(interior[:, None], q + noise[src], q)
+        pts[p0:p1] = q
+    return pts, off
+
+
 def make_atlas(spec: AtlasSpec, seed: int) -> Atlas:
     rng = _rng(seed, 0)
     cen = bezier_curves(rng, spec.n_centroids, spec.len_lo, spec.len_hi)
