@@ -107,6 +107,35 @@ def test_resample_interleaved_edges(seg):
     _same(_gpu_resample(seg, pts, off), oracle.resample_f32(pts, off), "interleaved")
 
 
+def test_resample_long_lines(seg):
+    """Streamlines of 500 to 3,000 points: most blocks cannot stage all of
+    their points and hand the rest to the lane path."""
+    rng = np.random.default_rng(13)
+    lines = [pins._raw_curve(rng, int(rng.integers(500, 3000)), rng.uniform(100, 250),
+                             rng.uniform([20, 20, 20], [60, 60, 60])) for _ in range(300)]
+    pts, off = pins._csr(lines)
+    log(f"resample long lines: {pts.shape[0]} points")
+    _same(_gpu_resample(seg, pts, off), oracle.resample_f32(pts, off), "long lines")
+
+
+def test_resample_overlap_after_bad(seg):
+    """Decreasing offsets: streamline 3 is invalid and streamline 4 re-reads
+    points of streamline 2; each valid one still equals the oracle on its own
+    points."""
+    fib, _ = synth.small_case(70, 2, 3, seed=14)
+    pts, off = synth.raw_streamlines(fib, np.random.default_rng(14))
+    bad = off.copy()
+    bad[4] = off[2] + 3  # streamline 3 = [off[3], off[2] + 3): decreasing
+    log("resample overlap after a bad streamline")
+    got = _gpu_resample(seg, pts, bad)
+    assert np.isnan(got[3]).all()
+    for i in range(70):
+        if i == 3:
+            continue
+        want = oracle.resample_f32(pts[bad[i]:bad[i + 1]], np.array([0, bad[i + 1] - bad[i]]))
+        assert np.array_equal(got[i], want[0]), i
+
+
 def test_resample_bad_offsets(seg):
     import torch
 
