@@ -78,6 +78,9 @@ class Oracle:
         L.oracle_arc_length_f32.restype = ctypes.c_float
         L.oracle_tn_f32.argtypes = [ctypes.c_float, ctypes.c_float]
         L.oracle_tn_f32.restype = ctypes.c_float
+        L.oracle_segment_multi_f32.argtypes = [P, i64, P, i64, P, P, i32, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, P, P, P, i64, P]
+        L.oracle_segment_multi_f32.restype = i64
         L.oracle_resample_f32.argtypes = [P, P, i64, i64, ctypes.c_int, P]
         L.oracle_resample_f32.restype = ctypes.c_int
         self.L = L
@@ -131,6 +134,30 @@ class Oracle:
 
     def tn_f32(self, ls: float, lc: float) -> float:
         return float(self.L.oracle_tn_f32(ls, lc))
+
+    def segment_multi_f32(self, fibers, centroids, bid, thr, flags: int = 0, mode: int = CUT,
+                          threads: int = 0):
+        """Every bundle each fiber passes: (offsets int64 [n + 1], bundles int32
+        [total], dists float32 [total], bundle_counts int64 [nb]); fiber f's
+        bundles (increasing) are bundles[offsets[f]:offsets[f + 1]]."""
+        keep, pf, pc, pb, pt = self._prep(fibers, centroids, bid, thr)
+        f, c, b, t = keep
+        n = f.shape[0]
+        offsets = np.zeros(n + 1, np.int64)
+        counts = np.zeros(max(t.shape[0], 1), np.int64)
+        total = self.L.oracle_segment_multi_f32(pf, n, pc, c.shape[0], pb, pt, t.shape[0], mode,
+                                                flags, threads, offsets.ctypes.data, None, None,
+                                                0, None)
+        if total < 0:
+            raise ValueError(f"oracle_segment_multi_f32 failed ({total})")
+        bundles = np.zeros(max(total, 1), np.int32)
+        dists = np.zeros(max(total, 1), np.float32)
+        total2 = self.L.oracle_segment_multi_f32(pf, n, pc, c.shape[0], pb, pt, t.shape[0], mode,
+                                                 flags, threads, offsets.ctypes.data,
+                                                 bundles.ctypes.data, dists.ctypes.data, total,
+                                                 counts.ctypes.data)
+        assert total2 == total
+        return offsets, bundles[:total], dists[:total], counts[:t.shape[0]]
 
     def resample_f32(self, points, offsets, threads: int = 0):
         """Raw streamlines (points [P, 3] float32, CSR offsets [n + 1] int64)
@@ -231,3 +258,7 @@ def segment_ext_f32(*a, **k):
 
 def resample_f32(*a, **k):
     return get().resample_f32(*a, **k)
+
+
+def segment_multi_f32(*a, **k):
+    return get().segment_multi_f32(*a, **k)

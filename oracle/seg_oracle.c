@@ -57,6 +57,15 @@
  *   dx * dx))) of p[i+1] - p[i], summed in point order; r = |lS - lC| / max
  *   (rounded once), u = r + 1, TN = u * u - 1 (each rounded); the complete
  *   metric sqrtf(D) + TN (rounded once).
+ * Several labels per fiber (oracle_segment_multi_f32), the classification of
+ *   the previous version of the algorithm (section 2.4, "Classification of
+ *   fibers": a fiber may be assigned to every bundle whose threshold test it
+ *   passes): the fiber is a member of bundle B when some centroid of B passes
+ *   the test above (with the metric variant's rules); its distance to B is
+ *   the smallest value over those centroids (sqrtf(D), or the complete
+ *   metric with VAR_TN).  Output: per fiber, its bundles in increasing id
+ *   with their distances, as rows of a CSR table, and the number of members
+ *   of each bundle.
  * Resampling (oracle_resample_f32), the step before the comparison: every
  *   subject fiber is brought to 21 points equidistant in arc length (section
  *   2.3, classification algorithm; section 2.2: the atlas centroids carry 21
@@ -388,6 +397,99 @@ int oracle_segment_ext_f32(const float* fibers, int64_t n, const float* cen, int
   free(lc);
   free(t2);
   return 0;
+}
+
+/* ---------------------------------------------------------------- several labels */
+
+/* Bundles of fiber a: best[b] = smallest accepted value over the centroids
+   of bundle b, seen[b] = whether any centroid of b was accepted. */
+static void multi_one_f32(const float* a, const float* cen, int64_t m, const int32_t* bid,
+                          const float* thr, const float* t2, const float* lc, int mode, int flags,
+                          float* best, char* seen) {
+  const float ls = oracle_arc_length_f32(a);
+  for (int64_t c = 0; c < m; ++c) {
+    float D;
+    const float* b = cen + (size_t)c * 3 * NP;
+    float tt = t2[bid[c]];
+    int ok;
+    if (flags & VAR_DIR)
+      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);
+    else
+      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);
+    if (!ok) continue;
+    float v = D;
+    if (flags & VAR_TN) {
+      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);
+      if (!(v <= thr[bid[c]])) continue;
+    }
+    int32_t k = bid[c];
+    if (!seen[k] || v < best[k]) best[k] = v;
+    seen[k] = 1;
+  }
+}
+
+/*
+ * Several labels per fiber.  offsets [n + 1]: fiber f's entries are
+ * bundles/dists[offsets[f] .. offsets[f+1]), bundles increasing; entries
+ * beyond `cap` are not written.  bundle_counts [nb] (may be NULL).  Returns
+ * the number of entries, or a negative error.
+ */
+int64_t oracle_segment_multi_f32(const float* fibers, int64_t n, const float* cen, int64_t m,
+                                 const int32_t* bid, const float* thr, int32_t nb, int mode,
+                                 int flags, int nthreads, int64_t* offsets, int32_t* bundles,
+                                 float* dists, int64_t cap, int64_t* bundle_counts) {
+  int rc = check_args(n, m, bid, nb);
+  if (rc) return rc;
+  const size_t nbs = (size_t)(nb > 0 ? nb : 1);
+  float* t2 = (float*)malloc(sizeof(float) * nbs);
+  float* lc = (float*)malloc(sizeof(float) * (size_t)(m > 0 ? m : 1));
+  for (int32_t b = 0; b < nb; ++b) t2[b] = thr2_f32(thr[b]);
+  for (int64_t c = 0; c < m; ++c) lc[c] = oracle_arc_length_f32(cen + (size_t)c * 3 * NP);
+  /* pass 1: number of bundles of each fiber; pass 2: the entries */
+  for (int pass = 0; pass < 2; ++pass) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+      float* best = (float*)malloc(sizeof(float) * nbs);
+      char* seen = (char*)malloc(nbs);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+      for (int64_t f = 0; f < n; ++f) {
+        memset(seen, 0, nbs);
+        multi_one_f32(fibers + (size_t)f * 3 * NP, cen, m, bid, thr, t2, lc, mode, flags, best,
+                      seen);
+        int64_t k = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+          if (!seen[b]) continue;
+          if (pass == 1) {
+            int64_t at = offsets[f] + k;
+            if (at < cap) {
+              bundles[at] = b;
+              dists[at] = (flags & VAR_TN) ? best[b] : sqrtf(best[b]);
+            }
+          }
+          ++k;
+        }
+        if (pass == 0) offsets[f + 1] = k;
+      }
+      free(seen);
+      free(best);
+    }
+    if (pass == 0) {
+      offsets[0] = 0;
+      for (int64_t f = 0; f < n; ++f) offsets[f + 1] += offsets[f];
+    }
+  }
+  if (bundle_counts) {
+    for (int32_t b = 0; b < nb; ++b) bundle_counts[b] = 0;
+    for (int64_t i = 0; i < offsets[n] && i < cap; ++i) bundle_counts[bundles[i]] += 1;
+  }
+  free(lc);
+  free(t2);
+  return offsets[n];
 }
 
 /* ---------------------------------------------------------------- resampling */

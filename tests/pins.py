@@ -598,6 +598,103 @@ def pin_resample_rounding_corners(O):
     assert np.array_equal(out[1][5], np.array([8388609.0, 0.0, 0.0], F32)), out[1][5]
 
 
+# ---------------------------------------------------------------- several labels
+
+def _overlapping_set(rng, n=300, nb=6, per=4):
+    """Bundles that share shapes: each base curve has shifted copies (0.5 to 3
+    mm) in two or three bundles, so many fibers pass several bundles."""
+    base = [_smooth_curve(rng, rng.uniform(30, 90), rng.uniform([30, 30, 30], [120, 150, 120]))
+            for _ in range(per * 2)]
+    cen, bid = [], []
+    for b in range(nb):
+        for k in range(per):
+            c = base[(b * per // 2 + k) % len(base)].astype(np.float64)
+            cen.append((c + rng.uniform(-3, 3, 3)[None, :]).astype(F32))
+            bid.append(b)
+    cen = np.stack(cen)
+    bid = np.array(bid, np.int32)
+    fib = np.stack([(base[rng.integers(len(base))].astype(np.float64)
+                     + rng.normal(0, 0.7, (21, 3)))[::(1 if rng.random() < 0.5 else -1)]
+                    .astype(F32) for _ in range(n)])
+    thr = rng.uniform(3.0, 6.0, nb).astype(F32)
+    return fib, cen, bid, thr
+
+
+def _rows(off, bun, dst):
+    return [(bun[off[f]:off[f + 1]], dst[off[f]:off[f + 1]]) for f in range(len(off) - 1)]
+
+
+def pin_multi_closed_form(O):
+    """Translated copies of a straight fiber (d_ME = |t|, exact): bundle 0 holds
+    copies at 3 and 1.5 mm (T = 2), bundle 1 at 1 and 2 mm (T = 2.5), bundle 2
+    at 5 mm (T = 4), bundle 3 none: the fiber is in bundles 0 (1.5) and 1 (1)."""
+    a = np.zeros((21, 3))
+    a[:, 0] = 40.0 + 2.0 * np.arange(21)
+    a[:, 1] = 60.0
+    a[:, 2] = 70.0
+    shifts = [(3.0, 0), (1.5, 0), (1.0, 1), (2.0, 1), (5.0, 2)]
+    cen = np.stack([a + np.array([0.0, t, 0.0]) for t, _ in shifts]).astype(F32)
+    bid = np.array([b for _, b in shifts], np.int32)
+    thr = np.array([2.0, 2.5, 4.0, 9.0], F32)
+    fib = np.stack([a, a[::-1]]).astype(F32)
+    for mode in (BRUTE, CUT):
+        off, bun, dst, cnt = O.segment_multi_f32(fib, cen, bid, thr, 0, mode=mode)
+        assert off.tolist() == [0, 2, 4]
+        assert bun.tolist() == [0, 1, 0, 1] and dst.tolist() == [1.5, 1.0, 1.5, 1.0]
+        assert cnt.tolist() == [2, 2, 0, 0]
+
+
+def pin_multi_single_consistency(O, seed=18):
+    """The closest-bundle label is one of the fiber's bundles, at the smallest
+    of its distances; unlabelled fibers have none; bundle counts are the
+    histogram of the entries; bundles increase within a fiber."""
+    rng = np.random.default_rng(seed)
+    fib, cen, bid, thr = _overlapping_set(rng)
+    for flags in (0, TN, DIR, TN | DIR):
+        off, bun, dst, cnt = O.segment_multi_f32(fib, cen, bid, thr, flags)
+        lab, dist, _ = O.segment_ext_f32(fib, cen, bid, thr, flags)
+        assert np.array_equal(cnt, np.bincount(bun, minlength=len(thr)))
+        for f, (b, d) in enumerate(_rows(off, bun, dst)):
+            assert (np.diff(b) > 0).all()
+            if lab[f] < 0:
+                assert b.size == 0
+            else:
+                assert lab[f] in b and d[list(b).index(lab[f])] == dist[f] == d.min()
+        if flags == 0:
+            assert (np.diff(off) >= 2).sum() > 30
+
+
+def pin_multi_infinite_thresholds(O, seed=19):
+    """T = +inf: every fiber is in every bundle with centroids, at the smallest
+    d_ME over the bundle (NumPy float64 brute force); T < 0: in none."""
+    rng = np.random.default_rng(seed)
+    fib, cen, bid, thr = _overlapping_set(rng, n=40)
+    bid = bid.copy()
+    bid[bid == 2] = 3  # bundle 2 has no centroids
+    inf = np.full(len(thr), np.inf, F32)
+    off, bun, dst, cnt = O.segment_multi_f32(fib, cen, bid, inf, 0)
+    d64 = np_fp64.dme_matrix(fib, cen)  # [n, m]
+    have = sorted(set(bid.tolist()))
+    assert np.array_equal(np.diff(off), np.full(len(fib), len(have)))
+    for f, (b, d) in enumerate(_rows(off, bun, dst)):
+        assert b.tolist() == have
+        want = np.array([d64[f, bid == k].min() for k in have])
+        assert np.allclose(d, want, rtol=1e-5, atol=1e-5)
+    assert cnt.tolist() == [len(fib) if k in have else 0 for k in range(len(thr))]
+    off, bun, dst, cnt = O.segment_multi_f32(fib, cen, bid, np.full(len(thr), -1.0, F32), 0)
+    assert off[-1] == 0 and cnt.sum() == 0
+
+
+def pin_multi_cut_equals_brute(O, seed=20):
+    """The paper's progressive discard gives the same entries as brute force."""
+    rng = np.random.default_rng(seed)
+    fib, cen, bid, thr = _overlapping_set(rng, n=150)
+    for flags in (0, TN, DIR):
+        a = O.segment_multi_f32(fib, cen, bid, thr, flags, mode=BRUTE)
+        b = O.segment_multi_f32(fib, cen, bid, thr, flags, mode=CUT)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 ALL_PINS = [
     pin_expression_rounding,
     pin_straight_translation,
@@ -623,4 +720,8 @@ ALL_PINS = [
     pin_resample_vs_interp,
     pin_resample_invariants,
     pin_resample_rounding_corners,
+    pin_multi_closed_form,
+    pin_multi_single_consistency,
+    pin_multi_infinite_thresholds,
+    pin_multi_cut_equals_brute,
 ]

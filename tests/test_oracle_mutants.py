@@ -52,6 +52,15 @@ MUTANTS = {
     "dir_picks_larger": ("int direct = ed <= ei;\n  float mx = direct ? ed : ei;", "int direct = ed > ei;\n  float mx = direct ? ed : ei;"),
     "dir_ignored_brute": ("if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);",
                           "if (flags & VAR_DIR)\n        ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);"),
+    "multi_first_found": ("if (!seen[k] || v < best[k]) best[k] = v;", "if (!seen[k]) best[k] = v;"),
+    "multi_last_found": ("if (!seen[k] || v < best[k]) best[k] = v;", "best[k] = v;"),
+    "multi_drops_last_bundle": ("for (int32_t b = 0; b < nb; ++b) {\n          if (!seen[b]) continue;",
+                                "for (int32_t b = 0; b < nb - 1; ++b) {\n          if (!seen[b]) continue;"),
+    "multi_squared_distance": ("dists[at] = (flags & VAR_TN) ? best[b] : sqrtf(best[b]);",
+                               "dists[at] = best[b];"),
+    "multi_counts_set_not_added": ("bundle_counts[bundles[i]] += 1;", "bundle_counts[bundles[i]] = 1;"),
+    "multi_threshold_of_bundle_zero": ("    float tt = t2[bid[c]];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k",
+                                       "    float tt = t2[0];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k"),
     "resample_k_over_21": ("float t = ((float)k * L) / 20.0f;", "float t = ((float)k * L) / 21.0f;"),
     "resample_strict_tie": ("while (j + 1 < P && !(t <= s[j + 1])) ++j;",
                             "while (j + 1 < P && !(t < s[j + 1])) ++j;"),
