@@ -192,6 +192,34 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     }, out
 
 
+def bench_multi(P, hip, f, c, b, t, head, args, N, np):
+    """Every bundle each fiber passes (CSR rows and bundle counts) on the
+    headline form; each call ends by reading the entry count back."""
+    import torch
+
+    hmode, _, htile = head.partition(":")
+    if hmode not in ("bf16", "fp16", "fp8"):
+        return None
+    sh = torch.cuda.current_stream().cuda_stream
+    atlas = P.Atlas(c, b, t)
+    for _ in range(args.warmup):
+        out = atlas.segment_multi(f, mode=hmode, tile=int(htile or 0))
+    torch.cuda.synchronize()
+    e0, e1 = hip.event(), hip.event()
+    hip.record(e0, sh)
+    for _ in range(args.steps):
+        out = atlas.segment_multi(f, mode=hmode, tile=int(htile or 0))
+    hip.record(e1, sh)
+    torch.cuda.synchronize()
+    ms = hip.elapsed(e0, e1) / args.steps
+    off = out[0].cpu().numpy()
+    per = np.bincount(np.diff(off))
+    atlas.close()
+    log(f"several labels on {head}: {ms:.3f} ms, {int(off[-1])} entries")
+    return {"ms": ms, "mode": head, "entries": int(off[-1]), "pairs_per_s": N * int(c.shape[0]) /
+            (ms * 1e-3), "fibers_by_bundle_count": {str(k): int(v) for k, v in enumerate(per)}}
+
+
 def bench_resample(P, hip, f, at, c, b, t, wl, head, args, N, np):
     """Raw streamlines of the workload's subject (0.2 mm steps, drawn on the
     device) to 21 points: the resampling kernel alone, HIP events on its
@@ -290,6 +318,8 @@ def main():
     ap.add_argument("--variants", default="tn,dir,tn+dir",
                     help="metric variants timed on the headline mode (Eq. 3 length "
                          "normalisation `tn`, section 2.4 direction inference `dir`)")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the several-labels leg (every bundle a fiber passes)")
     ap.add_argument("--no-resample", action="store_true",
                     help="skip the resampling leg (raw streamlines to 21 points)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -432,6 +462,7 @@ def main():
         log(f"variant {v} on {head}: {rv['ms_per_step']:.3f} ms/step, "
             f"{variants[v]['label_diffs_vs_exact']} labels differ from Eq. 2")
 
+    multi = None if args.no_multi else bench_multi(P, hip, f, c, b, t, head, args, N, np)
     resample = None if args.no_resample else bench_resample(P, hip, f, at, c, b, t, wl, head,
                                                             args, N, np)
 
@@ -479,6 +510,7 @@ def main():
                   for m, x in modes.items()},
         "roofline": roofline,
         "variants": variants,
+        "multi": multi,
         "resample": resample,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),

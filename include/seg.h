@@ -59,7 +59,8 @@ typedef enum seg_status {
   SEG_ENOMEM = -5,      /* scratch allocation failed */
   SEG_ERANGE = -6,      /* a size beyond what the kernels index (M >= 2^24) */
   SEG_EMODE = -7,       /* unknown mode or option value */
-  SEG_EOFFSETS = -8     /* an empty streamline or offsets outside the points (validate = 1) */
+  SEG_EOFFSETS = -8,    /* an empty streamline or offsets outside the points (validate = 1) */
+  SEG_ECAPACITY = -9    /* more label entries than the output holds (*total tells how many) */
 } seg_status;
 
 typedef enum seg_mode {
@@ -231,6 +232,40 @@ int seg_filter_pairs(const float* fibers, int64_t n_fibers, const float* centroi
                      int64_t n_centroids, const int32_t* centroid_bundle_id,
                      const float* bundle_thresholds, int32_t n_bundles, int32_t mode,
                      int32_t* pairs, int64_t capacity, int64_t* count, void* stream);
+
+/*
+ * Several labels per fiber: the classification of the algorithm's previous
+ * version (section 2.4, "Classification of fibers"), where a fiber belongs to
+ * every bundle whose threshold test it passes, not only the closest one.
+ *
+ * Fiber f is a member of bundle B when some centroid of B passes the
+ * threshold rule of seg_segment under opt->metric; its distance to B is the
+ * smallest over those centroids (d_ME in mm, or the complete metric with
+ * SEG_METRIC_LENGTH_NORM).  The closest-bundle label of seg_segment is the
+ * member of smallest distance.
+ *
+ * fibers         device, [n][21][3] float32.
+ * max_per_fiber  slots per fiber, 1..16: a fiber passing more bundles makes
+ *                the call return SEG_ERANGE (outputs then unspecified).
+ * offsets        device output, [n + 1] int64, 8-byte aligned: fiber f's
+ *                entries are bundles/dists[offsets[f] .. offsets[f+1]), its
+ *                bundles in increasing id (a CSR table).
+ * bundles, dists device outputs, [capacity] int32 / float32.
+ * total          host output: the number of entries (offsets[n]); when it
+ *                exceeds capacity the entries past it are not written and
+ *                the call returns SEG_ECAPACITY (call again with capacity >=
+ *                *total).
+ * bundle_counts  device output, [n_bundles] int64, 8-byte aligned, or NULL:
+ *                the number of member fibers of each bundle.
+ * opt            mode SEG_PREFILTER_BF16 / FP16 / FP8 (the tile-culled form,
+ *                tile 0 or 8; other modes return SEG_EMODE), metric, validate.
+ * Synchronises the stream (the total is read back).  Library scratch:
+ * 8 * max_per_fiber bytes per fiber.  Fewer than 2^31 fibers.
+ */
+int seg_segment_multi(const seg_atlas* atlas, const float* fibers, int64_t n,
+                      int32_t max_per_fiber, int64_t* offsets, int32_t* bundles, float* dists,
+                      int64_t capacity, int64_t* total, int64_t* bundle_counts,
+                      const seg_options* opt, void* stream);
 
 /*
  * Resampling of raw streamlines to 21 points equidistant in arc length: the

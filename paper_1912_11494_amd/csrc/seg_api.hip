@@ -78,6 +78,10 @@ struct Scratch {
   unsigned long long* counters = nullptr;  // [NCOUNTERS]
   seg::PrefilterBuf pre;
   seg::BatchBuf batch;
+  void* mslots = nullptr;  // several labels: per-fiber bundle slots
+  size_t mslots_bytes = 0;
+  void* mscan = nullptr;   // several labels: scan partials
+  size_t mscan_bytes = 0;
 
   int init() {
     if (!flags) HIP_TRY(hipMalloc(&flags, sizeof(unsigned long long)));
@@ -408,6 +412,95 @@ int seg_segment_atlas(const seg_atlas* a, const float* fibers, int64_t n, int32_
     if (rc) return rc;
   }
   return run_mode(o, a->buf, sc, fibers, n, labels, dists, s);
+}
+
+int seg_segment_multi(const seg_atlas* a, const float* fibers, int64_t n, int32_t max_per_fiber,
+                      int64_t* offsets, int32_t* bundles, float* dists, int64_t capacity,
+                      int64_t* total, int64_t* bundle_counts, const seg_options* opt,
+                      void* stream) {
+  t_err.clear();
+  if (!a) return fail(SEG_EINVAL, "null atlas");
+  if (!total) return fail(SEG_EINVAL, "null total pointer");
+  *total = 0;
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
+  if (rc) return rc;
+  if (o.mode != SEG_PREFILTER_BF16 && o.mode != SEG_PREFILTER_FP16 && o.mode != SEG_PREFILTER_FP8)
+    return fail(SEG_EMODE, "several labels per fiber use the tile-culled prefilter (bf16, fp16, fp8)");
+  if (o.tile != 0 && o.tile != 8)
+    return fail(SEG_EMODE, "several labels per fiber use the tile-culled form (tile 0 or 8)");
+  if (max_per_fiber < 1 || max_per_fiber > 16) return fail(SEG_EINVAL, "max_per_fiber must be 1..16");
+  if (n < 0 || capacity < 0) return fail(SEG_EINVAL, "negative fiber count or capacity");
+  if (n >= ((int64_t)1 << 31)) return fail(SEG_ERANGE, "several labels need fewer than 2^31 fibers");
+  if (!offsets || (n > 0 && !fibers) || (capacity > 0 && (!bundles || !dists)))
+    return fail(SEG_EINVAL, "null fiber/offset/entry pointer");
+  if (!aligned4(fibers) || !aligned4(bundles) || !aligned4(dists) || ((uintptr_t)offsets & 7u) ||
+      ((uintptr_t)bundle_counts & 7u))
+    return fail(SEG_EINVAL, "misaligned pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch* sc = nullptr;
+  rc = get_scratch(s, &sc);
+  if (rc) return rc;
+  if (o.validate && n > 0) {
+    if (seg::launch_fill_u64(sc->flags, 1, 0ull, s) ||
+        seg::launch_check_finite(fibers, n * 63, (unsigned int*)sc->flags, s))
+      return hip_fail(hipGetLastError(), "validation launch");
+    unsigned long long f = 0;
+    rc = read_flags(sc->flags, s, &f);
+    if (rc) return rc;
+    rc = flags_error(f);
+    if (rc) return rc;
+  }
+  const size_t sbytes = (size_t)(n > 0 ? n : 1) * max_per_fiber * sizeof(unsigned long long);
+  if (sbytes > sc->mslots_bytes) {
+    if (sc->mslots) (void)hipFree(sc->mslots);
+    sc->mslots = nullptr;
+    sc->mslots_bytes = 0;
+    if (hipMalloc(&sc->mslots, sbytes) != hipSuccess)
+      return fail(SEG_ENOMEM, "several-label slot allocation failed");
+    sc->mslots_bytes = sbytes;
+  }
+  unsigned long long* slots = (unsigned long long*)sc->mslots;
+  if (seg::launch_fill_zero_u64(slots, n * max_per_fiber, s) ||
+      seg::launch_fill_u64(sc->flags, 1, 0ull, s))
+    return hip_fail(hipGetLastError(), "slot reset");
+  unsigned long long* counters = o.collect_stats ? sc->counters : nullptr;
+  if (counters && seg::launch_fill_u64(counters, seg::NCOUNTERS, 0ull, s))
+    return hip_fail(hipGetLastError(), "counter reset");
+  if (n > 0 && a->buf.m > 0) {
+    const seg::Metric mt{a->buf.cext, o.metric};
+    const seg::MultiOut mo{slots, max_per_fiber, a->buf.bid, (unsigned int*)sc->flags};
+    rc = seg::run_cull(o.mode - SEG_PREFILTER_BF16, fibers, n, a->buf.cprep, (int32_t)a->buf.m,
+                       a->buf.bid, nullptr, nullptr, counters, mt, sc->pre,
+                       (hipEvent_t*)o.profile_events, s, &mo);
+    if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
+    if (rc) return hip_fail(hipGetLastError(), "kernel launch");
+  }
+  rc = seg::multi_collect(slots, max_per_fiber, n, offsets, bundles, dists, capacity,
+                          bundle_counts, a->n_bundles, o.metric, &sc->mscan, &sc->mscan_bytes, s);
+  if (rc == -3) return fail(SEG_ENOMEM, "scan scratch allocation failed");
+  if (rc) return hip_fail(hipGetLastError(), "several-label collection launch");
+  if (o.collect_stats) {
+    t_stats_counters = counters;
+    t_stats_stream = s;
+    t_stats_pairs = n * a->buf.m;
+    t_stats_n = n;
+    t_stats_labels = nullptr;
+    t_stats_mode = o.mode;
+    t_stats_culled = true;
+  }
+  unsigned long long f = 0;
+  rc = read_flags(sc->flags, s, &f);
+  if (rc) return rc;
+  int64_t tot = 0;
+  HIP_TRY(hipMemcpy(&tot, offsets + n, sizeof(tot), hipMemcpyDeviceToHost));
+  *total = tot;
+  if (f & seg::FLAG_MULTI)
+    return fail(SEG_ERANGE, "a fiber passes more bundles than max_per_fiber");
+  if (tot > capacity)
+    return fail(SEG_ECAPACITY, "more label entries (" + std::to_string(tot) + ") than capacity");
+  return SEG_OK;
 }
 
 int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, int64_t n,

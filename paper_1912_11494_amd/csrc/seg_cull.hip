@@ -37,6 +37,8 @@
 //      streaming prefilter.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstring>
 
@@ -450,9 +452,9 @@ __device__ __forceinline__ bool dense_pair(const float* a, const float* b, float
 // list.  Each lane loads its
 // fiber record (252 bytes, 4-byte aligned) and centroid record (256 bytes)
 // with 16-byte loads, all at once, then evaluates the pair; accepted pairs
-// fold into the per-fiber keys.  With STATS the staged exact_pair runs
-// instead, to count its tests.
-template <bool STATS, int QCAP>
+// fold into the per-fiber keys (with MULTI, into the fiber's bundle slots).
+// With STATS the staged exact_pair runs instead, to count its tests.
+template <bool STATS, int QCAP, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void exact_list_kernel(const int2* __restrict__ list,
                                                          const uint32_t* __restrict__ list_n,
                                                          int64_t nwaves,
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
                                                          const float* __restrict__ cprep,
                                                          unsigned long long* __restrict__ keys,
                                                          unsigned long long* __restrict__ counters,
-                                                         Metric mt) {
+                                                         Metric mt, MultiOut mo) {
   StageCounts sc{counters};
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves) return;
@@ -507,8 +509,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
         }
         ok = act && dense_pair(a, b, b[NF], D, mt.flags);
       }
-      if (ok && variant_value(D, (uint32_t)e.y, (mt.flags & MF_TN) ? arc_length(ar) : 0.0f, mt, v))
-        atomicMin(&keys[e.x], (unsigned long long)make_key(v, (uint32_t)e.y));
+      if (ok && variant_value(D, (uint32_t)e.y, (mt.flags & MF_TN) ? arc_length(ar) : 0.0f, mt, v)) {
+        if (MULTI)
+          multi_insert(mo.slots + (int64_t)e.x * mo.K, mo.K, (uint32_t)mo.bid[e.y], v, mo.flag);
+        else
+          atomicMin(&keys[e.x], (unsigned long long)make_key(v, (uint32_t)e.y));
+      }
     }
   };
   const uint32_t cnt = list_n[w];
@@ -522,9 +528,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
 // Waves of the culled kernel whose survivors overflowed: each lane takes one
 // of the wave's 64 sorted rows and evaluates its fiber against every
 // centroid (the full metric, no cut), keeping the lexicographic minimum of
-// (D, centroid) over accepted centroids.  Only for degenerate inputs (more
-// than 512 survivors per 64 fibers).
-template <bool STATS>
+// (D, centroid) over accepted centroids (with MULTI, every accepted pair goes
+// to the fiber's bundle slots).  Only for degenerate inputs (more than 512
+// survivors per 64 fibers).
+template <bool STATS, bool MULTI>
 __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict__ list_n,
                                                      int64_t nwaves,
                                                      const int32_t* __restrict__ perm, int64_t n,
@@ -532,7 +539,7 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
                                                      const float* __restrict__ cprep, int32_t m,
                                                      unsigned long long* __restrict__ keys,
                                                      unsigned long long* __restrict__ counters,
-                                                     Metric mt) {
+                                                     Metric mt, MultiOut mo) {
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves || !(list_n[w] & RESCUE)) return;
   unsigned long long naccepted = 0;
@@ -551,12 +558,16 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
     if (act && dense_pair(a, b, b[NF], D, mt.flags)) {
       ++naccepted;
       if (variant_value(D, (uint32_t)c, ls, mt, v)) {
-        const unsigned long long k = make_key(v, (uint32_t)c);
-        best = k < best ? k : best;
+        if (MULTI) {
+          multi_insert(mo.slots + f * mo.K, mo.K, (uint32_t)mo.bid[c], v, mo.flag);
+        } else {
+          const unsigned long long k = make_key(v, (uint32_t)c);
+          best = k < best ? k : best;
+        }
       }
     }
   }
-  if (act) keys[f] = best;
+  if (!MULTI && act) keys[f] = best;
   if (STATS && naccepted) atomicAdd(counters + 3, naccepted);
 }
 
@@ -885,7 +896,7 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
 template <int Q>
 int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, const int32_t* bid,
                 int32_t* labels, float* dists, unsigned long long* counters, Metric mt,
-                PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
+                PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo) {
   constexpr int EB = QTraits<Q>::bytes;
   const int64_t n_pad = (n + 255) / 256 * 256;
   const int32_t ncols_pad = (m + 31) / 32 * 32;
@@ -951,19 +962,24 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   else
     cull_kernel<Q, false><<<blocks, 256, 0, s>>>(job, counters);
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
+  const MultiOut mout = mo ? *mo : MultiOut{nullptr, 0, nullptr, nullptr};
+  auto exact = [&](auto stats, auto multi) {
+    constexpr bool ST = decltype(stats)::value, MU = decltype(multi)::value;
+    exact_list_kernel<ST, CULL_QCAP, MU><<<blocks, 256, 0, s>>>(
+        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt,
+        mout);
+    rescue_kernel<ST, MU><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m,
+                                                 fkeys, counters, mt, mout);
+  };
+  using T = std::true_type;
+  using F = std::false_type;
   if (counters)
-    exact_list_kernel<true, CULL_QCAP><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt);
+    mo ? exact(T{}, T{}) : exact(T{}, F{});
   else
-    exact_list_kernel<false, CULL_QCAP><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt);
-  if (counters)
-    rescue_kernel<true><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys,
-                                               counters, mt);
-  else
-    rescue_kernel<false><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m,
-                                                fkeys, counters, mt);
-  finalize_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, bid, labels, dists, mt.flags);
+    mo ? exact(F{}, T{}) : exact(F{}, F{});
+  if (!mo)
+    finalize_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, bid, labels, dists,
+                                                                mt.flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -971,13 +987,13 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
 
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s) {
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo) {
   if (n <= 0) return 0;
   if (n >= ((int64_t)1 << 31)) return -2;  // sorted rows are indexed with 32 bits
   switch (q) {
-    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
-    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
-    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
+    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
+    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
+    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
     default: return -2;
   }
 }

@@ -68,6 +68,40 @@ __device__ __forceinline__ float tn_term(float ls, float lc) {
   return uu - 1.0f;
 }
 
+// Several labels per fiber: K slots per fiber, each 0 (empty) or
+// (bundle + 1) << 32 | bits of the smallest value seen for that bundle (the
+// values are non-negative floats, so their bits order like the values).  A
+// fiber's slots only go from empty to a bundle and then down in value, so a
+// stale read is never wrong for long: a failed compare-and-swap returns the
+// current word.  A bundle that finds no free slot sets `flag`.
+constexpr unsigned int FLAG_MULTI = 8u;
+
+struct MultiOut {
+  unsigned long long* slots;  // [n][K] in input fiber order
+  int32_t K;
+  const int32_t* bid;         // bundle of each prepared centroid
+  unsigned int* flag;
+};
+
+__device__ __forceinline__ void multi_insert(unsigned long long* __restrict__ row, int K,
+                                             uint32_t bundle, float v,
+                                             unsigned int* __restrict__ flag) {
+  const unsigned long long tag = (unsigned long long)(bundle + 1u);
+  const unsigned long long e = (tag << 32) | (unsigned long long)__float_as_uint(v);
+  for (int k = 0; k < K; ++k) {
+    unsigned long long cur = __hip_atomic_load(row + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == 0ull) {
+      cur = atomicCAS(row + k, 0ull, e);
+      if (cur == 0ull) return;  // a new bundle of this fiber
+    }
+    if ((cur >> 32) == tag) {
+      atomicMin(row + k, e);
+      return;
+    }
+  }
+  atomicOr(flag, FLAG_MULTI);
+}
+
 // Value the argmin compares for an accepted pair (D <= T2): D itself, or with
 // MF_TN the complete metric sqrtf(D) + TN, which must not exceed T (else the
 // pair is dropped).  `ls` is the fiber's arc length (MF_TN only).

@@ -77,6 +77,12 @@ int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const flo
                       int32_t nb, float* cprep, float4* ccen, int32_t* bid_out, float* cext,
                       unsigned int* flags, hipStream_t s);
 int launch_check_finite(const float* v, int64_t count, unsigned int* flags, hipStream_t s);
+// seg_multi.hip: slot rows -> sorted rows, CSR offsets, entries and bundle
+// counts (see seg_segment_multi); flags is the device word of multi_insert
+int multi_collect(unsigned long long* slots, int32_t K, int64_t n, int64_t* offsets,
+                  int32_t* bundles, float* dists, int64_t capacity, int64_t* bundle_counts,
+                  int32_t nb, int mflags, void** scan_buf, size_t* scan_bytes, hipStream_t s);
+int launch_fill_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 // seg_resample.hip: raw streamlines (CSR) to [n][21][3]; flags may be null
 int launch_resample(const float* pts, int64_t npts, const int64_t* off, int64_t n, float* out,
                     unsigned int* flags, hipStream_t s);
@@ -105,7 +111,7 @@ int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s)
 // Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s);
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo = nullptr);
 
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,

@@ -38,7 +38,7 @@ MODES = {
 
 STATUS = {0: "SEG_OK", -1: "SEG_EINVAL", -2: "SEG_EBUNDLE", -3: "SEG_ENONFINITE",
           -4: "SEG_EHIP", -5: "SEG_ENOMEM", -6: "SEG_ERANGE", -7: "SEG_EMODE",
-          -8: "SEG_EOFFSETS"}
+          -8: "SEG_EOFFSETS", -9: "SEG_ECAPACITY"}
 
 
 class SegError(RuntimeError):
@@ -110,6 +110,9 @@ def lib():
         L.seg_tune_save.restype = ctypes.c_int
         L.seg_tune_load.argtypes = [ctypes.c_char_p]
         L.seg_tune_load.restype = ctypes.c_int
+        L.seg_segment_multi.argtypes = [P, P, i64, i32, P, P, P, i64, ctypes.POINTER(i64), P,
+                                        ctypes.POINTER(Options), P]
+        L.seg_segment_multi.restype = ctypes.c_int
         L.seg_resample.argtypes = [P, i64, P, i64, P, i32, P]
         L.seg_resample.restype = ctypes.c_int
         L.seg_segment_streamlines.argtypes = [P, P, i64, P, i64, P, P, P,
@@ -259,6 +262,7 @@ class Atlas:
         _check(rc)
         self.handle = h
         self.device = centroids.device
+        self.n_bundles = int(bundle_thresholds.shape[0])
 
     def __len__(self):
         return int(lib().seg_atlas_size(self.handle))
@@ -288,6 +292,36 @@ class Atlas:
                                      dists.data_ptr(), ctypes.byref(opt), _stream(stream))
         _check(rc)
         return labels, dists
+
+    def segment_multi(self, fibers, max_per_fiber=8, capacity=None, mode="fp16", validate=False,
+                      tile=0, stats=False, stream=None, events=None, metric=0):
+        """Every bundle each fiber passes (see seg_segment_multi): (offsets int64
+        [n + 1], bundles int32 [total], dists float32 [total], bundle_counts
+        int64 [n_bundles]).  Without `capacity`, a second call is made with the
+        exact capacity when the first guess (2 per fiber) is too small."""
+        _dev(fibers, torch.float32, (21, 3), "fibers")
+        n = fibers.shape[0]
+        dev = fibers.device
+        nb = self.n_bundles
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        counts = torch.empty(max(nb, 1), dtype=torch.int64, device=dev)
+        opt = options(mode, validate, tile, stats, events, metric)
+        cap = 2 * n if capacity is None else int(capacity)
+        for attempt in range(2):
+            bundles = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            dists = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+            total = ctypes.c_int64(0)
+            rc = lib().seg_segment_multi(self.handle, fibers.data_ptr(), n, int(max_per_fiber),
+                                         offsets.data_ptr(), bundles.data_ptr(), dists.data_ptr(),
+                                         cap, ctypes.byref(total), counts.data_ptr(),
+                                         ctypes.byref(opt), _stream(stream))
+            if rc == -9 and capacity is None and attempt == 0:
+                cap = int(total.value)
+                continue
+            _check(rc)
+            break
+        t = int(total.value)
+        return offsets, bundles[:t], dists[:t], counts[:nb]
 
     def segment_streamlines(self, points, offsets, mode="plain", validate=False, tile=0,
                             stats=False, stream=None, fibers=None, out=None, metric=0):
