@@ -80,6 +80,7 @@ struct Scratch {
   seg::BatchBuf batch;
   void* mslots = nullptr;  // several labels: per-fiber bundle slots
   size_t mslots_bytes = 0;
+  bool mslots_zero = false;  // every slot is 0 (each completed call leaves it so)
   void* mscan = nullptr;   // several labels: scan partials
   size_t mscan_bytes = 0;
 
@@ -460,11 +461,16 @@ int seg_segment_multi(const seg_atlas* a, const float* fibers, int64_t n, int32_
     if (hipMalloc(&sc->mslots, sbytes) != hipSuccess)
       return fail(SEG_ENOMEM, "several-label slot allocation failed");
     sc->mslots_bytes = sbytes;
+    sc->mslots_zero = false;
   }
   unsigned long long* slots = (unsigned long long*)sc->mslots;
-  if (seg::launch_fill_zero_u64(slots, n * max_per_fiber, s) ||
-      seg::launch_fill_u64(sc->flags, 1, 0ull, s))
+  // the collection clears the slots it reads, so only a new table (or one
+  // left by a failed launch) needs a full clear
+  if (!sc->mslots_zero &&
+      seg::launch_fill_zero_u64(slots, (int64_t)(sc->mslots_bytes / sizeof(unsigned long long)), s))
     return hip_fail(hipGetLastError(), "slot reset");
+  sc->mslots_zero = false;
+  if (seg::launch_fill_u64(sc->flags, 1, 0ull, s)) return hip_fail(hipGetLastError(), "flag reset");
   unsigned long long* counters = o.collect_stats ? sc->counters : nullptr;
   if (counters && seg::launch_fill_u64(counters, seg::NCOUNTERS, 0ull, s))
     return hip_fail(hipGetLastError(), "counter reset");
@@ -481,6 +487,7 @@ int seg_segment_multi(const seg_atlas* a, const float* fibers, int64_t n, int32_
                           bundle_counts, a->n_bundles, o.metric, &sc->mscan, &sc->mscan_bytes, s);
   if (rc == -3) return fail(SEG_ENOMEM, "scan scratch allocation failed");
   if (rc) return hip_fail(hipGetLastError(), "several-label collection launch");
+  sc->mslots_zero = true;
   if (o.collect_stats) {
     t_stats_counters = counters;
     t_stats_stream = s;

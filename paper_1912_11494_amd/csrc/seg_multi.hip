@@ -4,14 +4,16 @@
 // that bundle's passing centroids.
 //
 // The exact stage leaves, per fiber, up to K slots of (bundle + 1) << 32 |
-// value bits (multi_insert).  Here:
-//   1. multi_rows_kernel sorts each fiber's slots (the bundle sits in the
-//      high word, so the 64-bit order is the bundle order), moves them to the
-//      front of the row and writes the fiber's count;
+// value bits (multi_insert), which fills a row's lowest empty slot first: a
+// row's entries are a prefix of it.  Here:
+//   1. multi_rows_kernel counts each row's prefix (reading only up to its
+//      first empty slot) and sorts it when it has two entries or more (the
+//      bundle sits in the high word, so the 64-bit order is the bundle order);
 //   2. an exclusive scan turns the counts into CSR row offsets (n + 1);
-//   3. multi_emit_kernel writes (bundle, distance) entries at the offsets and
+//   3. multi_emit_kernel writes (bundle, distance) entries at the offsets,
 //      counts the members of each bundle (per-block LDS histograms when the
-//      atlas has at most 4,096 bundles).
+//      atlas has at most 4,096 bundles, a bounded number of blocks) and
+//      clears the slots it read, so the table is all zero for the next call.
 // Every step is deterministic: the output does not depend on the order in
 // which the exact stage found the pairs.
 #include <hip/hip_runtime.h>
@@ -35,29 +37,26 @@ __global__ __launch_bounds__(256) void multi_rows_kernel(unsigned long long* __r
   const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (f >= n) return;
   unsigned long long* __restrict__ row = slots + f * K;
-  unsigned long long r[KMAX];
   int c = 0;
+  while (c < K && row[c] != 0ull) ++c;
+  if (c >= 2) {
+    unsigned long long r[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const unsigned long long v = k < K ? row[k] : 0ull;
-    r[k] = v;
-    c += v != 0ull;
-  }
-  // odd-even transposition sort, empty slots (0) last
+    for (int k = 0; k < KMAX; ++k) r[k] = k < c ? row[k] : ~0ull;
+    // odd-even transposition sort; the padding (~0) stays last
 #pragma unroll
-  for (int pass = 0; pass < KMAX; ++pass) {
+    for (int pass = 0; pass < KMAX; ++pass) {
 #pragma unroll
-    for (int k = pass & 1; k + 1 < KMAX; k += 2) {
-      const unsigned long long a = r[k] ? r[k] : ~0ull, b = r[k + 1] ? r[k + 1] : ~0ull;
-      const bool sw = b < a;
-      const unsigned long long lo = sw ? r[k + 1] : r[k], hi = sw ? r[k] : r[k + 1];
-      r[k] = lo;
-      r[k + 1] = hi;
+      for (int k = pass & 1; k + 1 < KMAX; k += 2) {
+        const unsigned long long a = r[k], b = r[k + 1];
+        r[k] = b < a ? b : a;
+        r[k + 1] = b < a ? a : b;
+      }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-    if (k < K) row[k] = r[k];
+    for (int k = 0; k < KMAX; ++k)
+      if (k < c) row[k] = r[k];
+  }
   counts[f] = c;
 }
 
@@ -139,7 +138,7 @@ __global__ __launch_bounds__(SCAN_T) void scan_apply_kernel(int64_t* __restrict_
 }
 
 __global__ __launch_bounds__(256) void multi_emit_kernel(
-    const unsigned long long* __restrict__ slots, int K, int64_t n,
+    unsigned long long* __restrict__ slots, int K, int64_t n,
     const int64_t* __restrict__ offsets, int32_t* __restrict__ bundles, float* __restrict__ dists,
     int64_t capacity, unsigned long long* __restrict__ bcount, int32_t nb, int mflags) {
   __shared__ unsigned int s_hist[HIST_MAX];
@@ -147,13 +146,13 @@ __global__ __launch_bounds__(256) void multi_emit_kernel(
   if (lds)
     for (int i = threadIdx.x; i < nb; i += 256) s_hist[i] = 0u;
   __syncthreads();
-  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (f < n) {
+  for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < n; f += (int64_t)gridDim.x * 256) {
     const int64_t o = offsets[f];
     const int c = (int)(offsets[f + 1] - o);
-    const unsigned long long* __restrict__ row = slots + f * K;
+    unsigned long long* __restrict__ row = slots + f * K;
     for (int k = 0; k < c; ++k) {
       const unsigned long long e = row[k];
+      row[k] = 0ull;
       const int32_t b = (int32_t)(e >> 32) - 1;
       const float v = __uint_as_float((uint32_t)e);
       if (b < 0 || b >= nb) continue;  // bundle ids were checked with the atlas
@@ -209,7 +208,8 @@ int multi_collect(unsigned long long* slots, int32_t K, int64_t n, int64_t* offs
   scan_sums_kernel<<<(unsigned)nblk, SCAN_T, 0, s>>>(offsets, n, part);
   scan_parts_kernel<<<1, SCAN_T, 0, s>>>(part, nblk);
   scan_apply_kernel<<<(unsigned)nblk, SCAN_T, 0, s>>>(offsets, n, part, nblk);
-  multi_emit_kernel<<<fb, 256, 0, s>>>(slots, K, n, offsets, bundles, dists, capacity, bc, nb,
+  const unsigned eb = fb < 2048u ? fb : 2048u;  // grid-stride: one histogram flush per block
+  multi_emit_kernel<<<eb, 256, 0, s>>>(slots, K, n, offsets, bundles, dists, capacity, bc, nb,
                                        mflags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
