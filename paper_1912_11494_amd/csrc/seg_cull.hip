@@ -282,32 +282,46 @@ __global__ __launch_bounds__(256) void cell_key_kernel(const float* __restrict__
 // and error bound +inf (its box is unbounded).
 constexpr int PAY_WORDS = 4;
 
-// One lane per fiber: the lane reads its record (252 bytes, 4-byte aligned)
-// with 16-byte loads (the wave's loads cover a contiguous 16 KB), quantises
-// it and writes its payload and center-cell key.
+// One lane per fiber: a block of CF_BLOCK fibers copies its contiguous
+// records (CF_BLOCK x 252 bytes) into LDS with coalesced 16-byte loads, then
+// each lane quantises its own record from LDS (a stride of 63 words, no bank
+// conflict) and writes its payload, its center-cell key and the reset value
+// of its argmin key.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+constexpr int CF_BLOCK = 128;
 
 template <int Q>
-__global__ __launch_bounds__(256) void cull_fiber_kernel(const float* __restrict__ fibers, int64_t n,
-                                                         PfParams* __restrict__ prm,
-                                                         uint4* __restrict__ pay,
-                                                         uint32_t* __restrict__ keys) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __restrict__ fibers,
+                                                              int64_t n,
+                                                              PfParams* __restrict__ prm,
+                                                              uint4* __restrict__ pay,
+                                                              uint32_t* __restrict__ keys,
+                                                              unsigned long long* __restrict__ fkeys) {
+  __shared__ float s_rec[CF_BLOCK * NF];
+  const int tid = (int)threadIdx.x;
+  const int64_t f0 = (int64_t)blockIdx.x * CF_BLOCK;
+  const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
+  {
+    const float* __restrict__ src = fibers + f0 * NF;
+    const int nfl = cnt * NF;
+    const int n4 = nfl >> 2;
+#pragma unroll 4
+    for (int i = tid; i < n4; i += CF_BLOCK) {
+      const f4u v = *(const f4u*)(src + 4 * i);
+      s_rec[4 * i] = v.x;
+      s_rec[4 * i + 1] = v.y;
+      s_rec[4 * i + 2] = v.z;
+      s_rec[4 * i + 3] = v.w;
+    }
+    if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = src[4 * n4 + tid];
+  }
+  __syncthreads();
+  const int64_t f = f0 + tid;
   float e32 = 0.0f;
-  if (f < n) {
-    const float* src = fibers + f * NF;
+  if (tid < cnt) {
     float rec[NF];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      const f4u v = *(const f4u*)(src + 4 * k);
-      rec[4 * k] = v.x;
-      rec[4 * k + 1] = v.y;
-      rec[4 * k + 2] = v.z;
-      rec[4 * k + 3] = v.w;
-    }
-    rec[60] = src[60];
-    rec[61] = src[61];
-    rec[62] = src[62];
+    for (int k = 0; k < NF; ++k) rec[k] = s_rec[tid * NF + k];
     uint4* P = pay + f * PAY_WORDS;
     if (QTraits<Q>::bytes == 1) P[1] = make_uint4(0u, 0u, 0u, 0u);
     double nq, e;
@@ -326,10 +340,11 @@ __global__ __launch_bounds__(256) void cull_fiber_kernel(const float* __restrict
     P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)f, 0u);
     P[3] = make_uint4(0u, 0u, 0u, 0u);
     keys[f] = center_cell(rec, prm);
+    fkeys[f] = NO_KEY;
   }
   for (int off = 32; off > 0; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off));
-  if ((threadIdx.x & 63) == 0)
-    atomicMax(&prm->emax_bits[(blockIdx.x * 4 + (threadIdx.x >> 6)) % EMAX_SLOTS],
+  if ((tid & 63) == 0)
+    atomicMax(&prm->emax_bits[(blockIdx.x * (CF_BLOCK / 64) + (tid >> 6)) % EMAX_SLOTS],
               __float_as_uint(e32));
 }
 
@@ -937,7 +952,10 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   uint32_t* hist = (uint32_t*)pb.hist;
   if (launch_pf_setup(prm, cprep, m, s)) return -1;
   // fibers: payloads and cell keys in input order, then the sort
-  cull_fiber_kernel<Q><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fibers, n, prm, pay, keys_a);
+  unsigned long long* fkeys = (unsigned long long*)pb.fkeys;
+  unsigned long long* ovf_count = fkeys + n;
+  cull_fiber_kernel<Q><<<(unsigned)((n + CF_BLOCK - 1) / CF_BLOCK), CF_BLOCK, 0, s>>>(
+      fibers, n, prm, pay, keys_a, fkeys);
   if (radix_sort(n, keys_a, keys_b, vals_a, vals_b, hist, nullptr, nullptr, s)) return -1;
   // centroids: cell keys, sort, then sorted columns with tile boxes
   if (m > 0) {
@@ -946,9 +964,6 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   }
   cull_column_kernel<Q><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
       cprep, m, ncols_pad, cperm, prm, cfeat, cbias, ccent, (float*)pb.tbox);
-  unsigned long long* fkeys = (unsigned long long*)pb.fkeys;
-  unsigned long long* ovf_count = fkeys + n;
-  fill_u64_n_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, NO_KEY);
   fill_u64_n_kernel<<<1, 64, 0, s>>>(ovf_count, 1, 0ull);
   int2* list = (int2*)pb.list;
   int2* ovf = list + nwaves * CULL_QCAP;
