@@ -48,14 +48,18 @@ TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf
                    ("seg::prefilter_kernel<1,", "prefilter_kernel:fp16"),
                    ("seg::prefilter_kernel<2,", "prefilter_kernel:fp8"),
                    ("seg::plain_kernel<", "plain_kernel"),
-                   ("seg::dense_kernel<1>", "dense_kernel"),
+                   ("seg::dense_kernel<1, false>", "dense_kernel"),
+                   ("seg::(anonymousnamespace)::cull_fiber_kernel<1>", "cull_fiber_kernel:fp16"),
+                   ("seg::(anonymousnamespace)::exact_list_kernel<false, 512, false>",
+                    "exact_list_kernel"),
                    ("seg::(anonymousnamespace)::resample_kernel", "resample_kernel")]
 KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
                   "paper_1912_11494_amd/csrc/seg_pf.hpp",
                   "paper_1912_11494_amd/csrc/seg_kernels.hip",
                   "paper_1912_11494_amd/csrc/seg_prefilter.hip",
                   "paper_1912_11494_amd/csrc/seg_cull.hip",
-                  "paper_1912_11494_amd/csrc/seg_resample.hip"]
+                  "paper_1912_11494_amd/csrc/seg_resample.hip",
+                  "paper_1912_11494_amd/csrc/seg_multi.hip"]
 
 
 def log(msg):
@@ -128,16 +132,30 @@ def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
                     acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return acc
 
+    def copy_dispatches(path, counter):
+        out = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and "copy" in r["Kernel_Name"].lower():
+                    out[r["Dispatch_Id"]] = (r["Kernel_Name"], float(r["Counter_Value"]))
+        return out
+
     fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
-    copies = [k for k in fe if "copy" in k.lower()]
-    if not copies:
-        raise SystemExit("no copy kernel in the counter file: run with --copy-probe")
-    big = max(copies, key=lambda k: max(fe[k]))
+    # the probe's copies: the copy dispatches that wrote 1 GiB (the write
+    # counter counts KiB), matched by dispatch id in the fetch run (the two
+    # runs launch the same sequence)
     gib = float(1 << 30)
-    cf = gib / (max(fe[big]) * 1024.0)
-    cw = gib / (max(wr[big]) * 1024.0)
-    out = {"calibration": {"kernel": big, "fetch_kib": max(fe[big]), "write_kib": max(wr[big]),
-                           "bytes_per_kib_fetch": cf, "bytes_per_kib_write": cw,
+    cwr = copy_dispatches(write_csv, "WRITE_SIZE")
+    cfe = copy_dispatches(fetch_csv, "FETCH_SIZE")
+    probe = [d for d, (_, v) in cwr.items() if abs(v * 1024.0 - gib) < 1e-3 * gib and d in cfe]
+    if not probe:
+        raise SystemExit("no 1 GiB copy in the counter files: run with --copy-probe")
+    fk = sum(cfe[d][1] for d in probe) / len(probe)
+    wk = sum(cwr[d][1] for d in probe) / len(probe)
+    cf = gib / (fk * 1024.0)
+    cw = gib / (wk * 1024.0)
+    out = {"calibration": {"kernel": cwr[probe[0]][0], "dispatches": len(probe), "fetch_kib": fk,
+                           "write_kib": wk, "bytes_per_kib_fetch": cf, "bytes_per_kib_write": cw,
                            "note": "a 1 GiB device copy (reads 1 GiB, writes 1 GiB) fixes "
                                    "the byte value of one counted KiB"}}
     for prefix, key in TRAFFIC_KERNELS:
