@@ -210,6 +210,83 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     }, out
 
 
+def bench_batch(args):
+    """The batch workload: 16 subjects (0.3M-4.1M fibers) against two atlases
+    (3,600 and 10,000 centroids), one label per (fiber, atlas).  Times the
+    batch entry point (one flattened launch per atlas group in a cached HIP
+    graph) and sequential one-subject calls, and checks that they agree."""
+    import numpy as np
+    import torch
+
+    import paper_1912_11494_amd as P
+    import synth
+
+    wl = "batch-16-subjects-x-2-atlases"
+    atl = synth.workload_atlases(wl)
+    subs = synth.workload_subjects(wl)
+    seed = synth.workload_seed(wl)
+    d = torch.device("cuda:0")
+    t0 = time.time()
+    gf = []
+    for i, sp in enumerate(subs):
+        gf.append(torch.from_numpy(synth.make_fibers(atl, sp, seed, subject_idx=i, workers=16)).to(d))
+    nf = sum(int(f.shape[0]) for f in gf)
+    log(f"generated {wl}: {nf} fibers in {time.time() - t0:.1f}s")
+    ga = [P.Atlas(torch.from_numpy(a.centroids).to(d), torch.from_numpy(a.bundle_id).to(d),
+                  torch.from_numpy(a.thresholds).to(d)) for a in atl]
+    pairs = nf * sum(a.n_centroids for a in atl)
+    hip = Hip()
+    sh = torch.cuda.current_stream().cuda_stream
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = hip.event(), hip.event()
+        hip.record(e0, sh)
+        for _ in range(args.steps):
+            fn()
+        hip.record(e1, sh)
+        torch.cuda.synchronize()
+        return hip.elapsed(e0, e1) / args.steps
+
+    def new_outs():
+        return [[(torch.empty(f.shape[0], dtype=torch.int32, device=d),
+                  torch.empty(f.shape[0], dtype=torch.float32, device=d)) for _ in ga] for f in gf]
+
+    res, labels = {}, {}
+    for mode, tile in (("plain", 0), ("bf16", 1), ("fp16", 1), ("fp16", 0), ("bf16", 0)):
+        outs = new_outs()
+        ms = timed(lambda: P.segment_batch(ga, gf, mode=mode, tile=tile, outs=outs))
+        res[f"batch {mode}:{tile}"] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3)}
+        labels[f"batch {mode}:{tile}"] = outs
+        log(f"batch {mode}:{tile}: {ms:.2f} ms")
+    for mode in ("fp16", "bf16"):
+        outs = new_outs()
+
+        def seq():
+            for i, f in enumerate(gf):
+                for a, at in enumerate(ga):
+                    at.segment(f, mode=mode, out=outs[i][a])
+
+        ms = timed(seq)
+        res[f"sequential {mode}"] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3)}
+        labels[f"sequential {mode}"] = outs
+        log(f"sequential {mode} (tile-culled): {ms:.2f} ms")
+    ref = labels["batch plain:0"]
+    diffs = {k: int(sum(int((o[i][a][0] != ref[i][a][0]).sum()) for i in range(len(gf))
+                        for a in range(len(ga)))) for k, o in labels.items()}
+    best = min(res, key=lambda k: res[k]["ms"])
+    print(json.dumps({"metric": "fiber-centroid pairs/s, batch of 16 subjects x 2 atlases",
+                      "value": res[best]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[best]["ms"],
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f16+f32" if "fp16" in best else "f32", "data": "synthetic",
+                      "config": {"workload": f"{wl}: {nf} fibers, 3,600 + 10,000 centroids",
+                                 "fibers": nf, "best": best},
+                      "paths": res, "label_diffs_vs_batch_plain": diffs}), flush=True)
+
+
 def bench_multi(P, hip, f, c, b, t, head, args, N, np):
     """Every bundle each fiber passes (CSR rows and bundle counts) on the
     headline form; each call ends by reading the entry count back."""
@@ -336,6 +413,8 @@ def main():
     ap.add_argument("--variants", default="tn,dir,tn+dir",
                     help="metric variants timed on the headline mode (Eq. 3 length "
                          "normalisation `tn`, section 2.4 direction inference `dir`)")
+    ap.add_argument("--batch", action="store_true",
+                    help="time the batch workload (16 subjects x 2 atlases) instead of one subject")
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the several-labels leg (every bundle a fiber passes)")
     ap.add_argument("--no-resample", action="store_true",
@@ -363,6 +442,9 @@ def main():
 
     import synth
 
+    if args.batch:
+        bench_batch(args)
+        return
     wl = args.workload
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]

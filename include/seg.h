@@ -180,12 +180,17 @@ int seg_segment_atlas(const seg_atlas* atlas, const float* fibers, int64_t n_fib
                       int32_t* labels, float* dists, const seg_options* opt, void* stream);
 
 /*
- * Segment n_subjects subjects against n_atlases prepared atlases with one
- * launch of the fused kernel over a flattened list of (subject, atlas, fiber
- * block) work items, costliest atlas first; the whole sequence (preparation
- * kernels + that launch) is captured once per launch shape into a HIP graph
- * and replayed on `stream`.  All subjects share one quantisation frame, so
- * each subject's prefilter features are computed once for all atlases.
+ * Segment n_subjects subjects against n_atlases prepared atlases in one call.
+ * SEG_PLAIN, SEG_PREFILTER_BF16_ORIENTED and the streaming tiles of the
+ * symmetric prefilters run one launch of the fused kernel over a flattened
+ * list of (subject, atlas, fiber block) work items, costliest atlas first;
+ * the whole sequence (preparation kernels + that launch) is captured once per
+ * launch shape into a HIP graph and replayed on `stream`, and all subjects
+ * share one quantisation frame, so each subject's prefilter features are
+ * computed once for all atlases.  SEG_PREFILTER_BF16 / FP16 / FP8 at tile 0
+ * (or 8) run the sorted, tile-culled form for each (subject, atlas) pair in
+ * turn on `stream` (no graph), which is faster on batches of large subjects.
+ * Every route gives each pair the result of the one-subject call.
  *   atlases   host array [n_atlases] of handles
  *   fibers    host array [n_subjects] of device pointers ([n][21][3] float32)
  *   n_fibers  host array [n_subjects]

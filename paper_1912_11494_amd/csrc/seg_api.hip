@@ -589,6 +589,31 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
   for (int32_t i = 0; i < n_subjects; ++i) nmax = n_fibers[i] > nmax ? n_fibers[i] : nmax;
   for (const auto& a : bav) mmax = a.m > mmax ? a.m : mmax;
   const int tile = o.tile ? o.tile : tuned_tile(o.mode, nmax, mmax);
+  const bool culled = o.mode >= SEG_PREFILTER_BF16 && o.mode <= SEG_PREFILTER_FP8 &&
+                      (tile == 0 || tile == 8) && nmax < ((int64_t)1 << 31);
+  if (culled) {
+    // the sorted, tile-culled form, one (subject, atlas) pair after another on
+    // the stream: faster than the flattened streaming launch on batches of
+    // large subjects, and each pair's result is the one-subject call's
+    for (int32_t i = 0; i < n_subjects; ++i) {
+      if (n_fibers[i] == 0) continue;
+      for (int32_t a = 0; a < n_atlases; ++a) {
+        int32_t* lab = labels[i * n_atlases + a];
+        float* dst = dists[i * n_atlases + a];
+        if (bav[a].m == 0) {
+          if (seg::launch_fill_empty(n_fibers[i], lab, dst, s))
+            return hip_fail(hipGetLastError(), "fill");
+          continue;
+        }
+        rc = seg::run_cull(o.mode - SEG_PREFILTER_BF16, fibers[i], n_fibers[i], bav[a].cprep,
+                           bav[a].m, bav[a].bid, lab, dst, nullptr,
+                           seg::Metric{bav[a].cext, o.metric}, sc->pre, nullptr, s);
+        if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
+        if (rc) return hip_fail(hipGetLastError(), "kernel launch");
+      }
+    }
+    return SEG_OK;
+  }
   rc = seg::run_batch(o.mode, tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
                       dists, o.metric, sc->batch, sc->pre, s);
   if (rc == -2) return fail(SEG_EMODE, "mode not supported by the batch path");

@@ -51,8 +51,11 @@ def _gpu_atlas(seg, at):
                      torch.from_numpy(at.thresholds).to(d))
 
 
-@pytest.mark.parametrize("mode", ["plain", "bf16", "fp16", "bf16_oriented"])
-def test_batch_matches_oracle(seg, mode):
+@pytest.mark.parametrize("mode,tile", [("plain", 0), ("bf16", 1), ("fp16", 1), ("bf16_oriented", 0),
+                                       ("bf16", 0), ("fp16", 0), ("fp8", 0), ("fp16", 8)])
+def test_batch_matches_oracle(seg, mode, tile):
+    """Graph-captured flattened launches (plain, oriented, streaming tiles) and
+    the per-pair tile-culled route (tile 0 / 8 of bf16, fp16, fp8)."""
     import torch
 
     atl = _atlases()
@@ -60,8 +63,8 @@ def test_batch_matches_oracle(seg, mode):
     d = torch.device("cuda:0")
     ga = [_gpu_atlas(seg, a) for a in atl]
     gf = [torch.from_numpy(f).to(d) for f in subs]
-    log(f"batch mode={mode}")
-    outs = seg.segment_batch(ga, gf, mode=mode)
+    log(f"batch mode={mode} tile={tile}")
+    outs = seg.segment_batch(ga, gf, mode=mode, tile=tile)
     torch.cuda.synchronize()
     for i, f in enumerate(subs):
         for a, at in enumerate(atl):
@@ -95,7 +98,7 @@ def test_batch_graph_replay_and_reshape(seg):
         for o in outs:
             for lab, dist in o:
                 lab.fill_(-7)
-        seg.segment_batch(ga, gf, mode="bf16", outs=outs)
+        seg.segment_batch(ga, gf, mode="bf16", tile=1, outs=outs)
         torch.cuda.synchronize()
         # eager work between replays
         l_e, _ = ga[0].segment(gf[0], mode="plain")
@@ -108,7 +111,7 @@ def test_batch_graph_replay_and_reshape(seg):
     new = _subjects(atl, [900, 1300], seed=6)
     for g, f in zip(gf, new):
         g.copy_(torch.from_numpy(f).to(d))
-    seg.segment_batch(ga, gf, mode="bf16", outs=outs)
+    seg.segment_batch(ga, gf, mode="bf16", tile=1, outs=outs)
     torch.cuda.synchronize()
     for i, f in enumerate(new):
         for a, at in enumerate(atl):
@@ -136,11 +139,13 @@ def test_batch_empty_atlas(seg):
     assert len(empty) == 0
     subs = _subjects(atl, [400], seed=9)
     gf = [torch.from_numpy(subs[0]).to(d)]
-    outs = seg.segment_batch([empty, _gpu_atlas(seg, atl[1])], gf, mode="bf16")
-    torch.cuda.synchronize()
-    assert (outs[0][0][0] == -1).all() and torch.isinf(outs[0][0][1]).all()
-    l32 = oracle.segment_f32(subs[0], atl[1].centroids, atl[1].bundle_id, atl[1].thresholds)[0]
-    assert np.array_equal(outs[0][1][0].cpu().numpy(), l32)
+    for tile in (1, 0):
+        outs = seg.segment_batch([empty, _gpu_atlas(seg, atl[1])], gf, mode="bf16", tile=tile)
+        torch.cuda.synchronize()
+        assert (outs[0][0][0] == -1).all() and torch.isinf(outs[0][0][1]).all()
+        l32 = oracle.segment_f32(subs[0], atl[1].centroids, atl[1].bundle_id,
+                                 atl[1].thresholds)[0]
+        assert np.array_equal(outs[0][1][0].cpu().numpy(), l32)
 
 
 def test_autotune_roundtrip(seg, tmp_path):

@@ -139,9 +139,9 @@ def test_variant_batch(seg, metric):
     subs = [synth.make_fibers(atl, synth.SubjectSpec(n, 2.0, (0.2, 0.2)), 43, subject_idx=i)
             for i, n in enumerate([700, 1300])]
     gf = [torch.from_numpy(f).to(d) for f in subs]
-    for mode in ("plain", "bf16"):
-        log(f"variant batch {metric} mode={mode}")
-        outs = seg.segment_batch(ga, gf, mode=mode, metric=metric)
+    for mode, tile in (("plain", 0), ("bf16", 1), ("bf16", 0)):
+        log(f"variant batch {metric} mode={mode} tile={tile}")
+        outs = seg.segment_batch(ga, gf, mode=mode, tile=tile, metric=metric)
         torch.cuda.synchronize()
         for i, f in enumerate(subs):
             for a, at in enumerate(atl):
