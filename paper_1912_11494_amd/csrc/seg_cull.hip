@@ -165,14 +165,6 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scan_rows_kernel(uint32_t* __re
   if (tid == 0) tot[blockIdx.x] = carry;
 }
 
-// Exclusive scan of the digit totals (one block).
-__global__ __launch_bounds__(RS_THREADS) void rs_scan_digits_kernel(uint32_t* __restrict__ tot) {
-  __shared__ uint32_t s_tmp[RS_THREADS];
-  uint32_t all;
-  const uint32_t ex = block_exclusive_scan(tot[threadIdx.x], s_tmp, &all);
-  tot[threadIdx.x] = ex;
-}
-
 // Stable scatter.  Item i of wave w of block b has the block-local position
 //   (items of smaller digits in b) + (items of digit d in earlier waves of b)
 //   + (items of digit d earlier in this wave's range),
@@ -180,14 +172,16 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scan_digits_kernel(uint32_t* __
 // the lanes below with the same digit (a match mask built from 8 ballots).
 // Items are first placed in LDS at that position, then written out in
 // block-local order: item k of digit d goes to
-//   base[d] + hist[d][b] + (k - local start of d),
+//   start[d] + hist[d][b] + (k - local start of d),
+// where start[d] (the exclusive scan of the digit totals) is computed by
+// every block from the totals,
 // so each digit's run of the block is written contiguously.  With PAYLOAD,
 // the 64-byte record of each item's value moves along (the last pass of the
 // fiber sort gathers the fiber payloads into sorted order).
 template <bool PAYLOAD>
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n,
-    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dbase,
+    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
     int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out,
     const uint4* __restrict__ pay_in, uint4* __restrict__ pay_out) {
   constexpr int WAVES = RS_THREADS / 64;
@@ -218,8 +212,10 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     }
     uint32_t all;
     uint32_t l = block_exclusive_scan(tot, s_tmp, &all);
+    // start of digit d over all blocks: exclusive scan of the digit totals
+    const uint32_t dstart = block_exclusive_scan(dtot[d], s_tmp, &all);
     s_lstart[d] = l;
-    s_gstart[d] = dbase[d] + hist[(int64_t)d * nblocks + blockIdx.x];
+    s_gstart[d] = dstart + hist[(int64_t)d * nblocks + blockIdx.x];
     for (int w = 0; w < WAVES; ++w) {
       s_cnt[w][d] = l;
       l += c[w];
@@ -555,35 +551,38 @@ __global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict_
                                                      unsigned long long* __restrict__ keys,
                                                      unsigned long long* __restrict__ counters,
                                                      Metric mt, MultiOut mo) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= nwaves || !(list_n[w] & RESCUE)) return;
-  unsigned long long naccepted = 0;
-  const int64_t row = w * 64 + (threadIdx.x & 63);
-  const bool act = row < n;
-  const int64_t f = act ? (int64_t)perm[row] : 0;
-  float a[NF];
-  const float* ar = fibers + f * NF;
+  // a bounded grid walks every wave's flag; almost all are clear
+  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < nwaves;
+       w += (int64_t)gridDim.x * 4) {
+    if (!(list_n[w] & RESCUE)) continue;
+    unsigned long long naccepted = 0;
+    const int64_t row = w * 64 + (threadIdx.x & 63);
+    const bool act = row < n;
+    const int64_t f = act ? (int64_t)perm[row] : 0;
+    float a[NF];
+    const float* ar = fibers + f * NF;
 #pragma unroll
-  for (int k = 0; k < NF; ++k) a[k] = ar[k];
-  const float ls = (mt.flags & MF_TN) ? arc_length(a) : 0.0f;
-  unsigned long long best = NO_KEY;
-  for (int32_t c = 0; c < m; ++c) {
-    const float* b = cprep + (size_t)c * CREC;  // the same for every lane
-    float D, v;
-    if (act && dense_pair(a, b, b[NF], D, mt.flags)) {
-      ++naccepted;
-      if (variant_value(D, (uint32_t)c, ls, mt, v)) {
-        if (MULTI) {
-          multi_insert(mo.slots + f * mo.K, mo.K, (uint32_t)mo.bid[c], v, mo.flag);
-        } else {
-          const unsigned long long k = make_key(v, (uint32_t)c);
-          best = k < best ? k : best;
+    for (int k = 0; k < NF; ++k) a[k] = ar[k];
+    const float ls = (mt.flags & MF_TN) ? arc_length(a) : 0.0f;
+    unsigned long long best = NO_KEY;
+    for (int32_t c = 0; c < m; ++c) {
+      const float* b = cprep + (size_t)c * CREC;  // the same for every lane
+      float D, v;
+      if (act && dense_pair(a, b, b[NF], D, mt.flags)) {
+        ++naccepted;
+        if (variant_value(D, (uint32_t)c, ls, mt, v)) {
+          if (MULTI) {
+            multi_insert(mo.slots + f * mo.K, mo.K, (uint32_t)mo.bid[c], v, mo.flag);
+          } else {
+            const unsigned long long k = make_key(v, (uint32_t)c);
+            best = k < best ? k : best;
+          }
         }
       }
     }
+    if (!MULTI && act) keys[f] = best;
+    if (STATS && naccepted) atomicAdd(counters + 3, naccepted);
   }
-  if (!MULTI && act) keys[f] = best;
-  if (STATS && naccepted) atomicAdd(counters + 3, naccepted);
 }
 
 // labels / distances of every fiber from its key.
@@ -894,7 +893,6 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
     const uint32_t* kin = pass == 0 ? keys_a : keys_b;
     rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, shift, hist, nblocks);
     rs_scan_rows_kernel<<<RS_BINS, RS_THREADS, 0, s>>>(hist, nblocks, tot);
-    rs_scan_digits_kernel<<<1, RS_THREADS, 0, s>>>(tot);
     if (pass == 0)
       rs_scatter_kernel<false><<<nblocks, RS_THREADS, 0, s>>>(
           keys_a, nullptr, n, shift, hist, tot, nblocks, keys_b, vals_a, nullptr, nullptr);
@@ -983,8 +981,8 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
     exact_list_kernel<ST, CULL_QCAP, MU><<<blocks, 256, 0, s>>>(
         list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt,
         mout);
-    rescue_kernel<ST, MU><<<blocks, 256, 0, s>>>(list_n, nwaves, vals_b, n, fibers, cprep, m,
-                                                 fkeys, counters, mt, mout);
+    rescue_kernel<ST, MU><<<blocks < 1024u ? blocks : 1024u, 256, 0, s>>>(
+        list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys, counters, mt, mout);
   };
   using T = std::true_type;
   using F = std::false_type;
