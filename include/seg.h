@@ -296,7 +296,8 @@ int seg_segment_multi(const seg_atlas* atlas, const float* fibers, int64_t n,
  *   a single point gives 21 copies of it.
  * A streamline with no points, or whose offsets leave [0, n_points] or
  * decrease, gets 21 NaN points and no read of `points`; with validate = 1
- * the call synchronises the stream and returns SEG_EOFFSETS for it.
+ * the call synchronises the stream and returns SEG_EOFFSETS for it, or
+ * SEG_ENONFINITE for a NaN / inf coordinate among the n_points points.
  * n = 0 returns SEG_OK without launching.
  */
 int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, int64_t n,

@@ -529,6 +529,8 @@ int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, 
     if (seg::launch_fill_u64(sc->flags, 1, 0ull, s)) return hip_fail(hipGetLastError(), "flag reset");
     flags = (unsigned int*)sc->flags;
   }
+  if (validate && n_points > 0 && seg::launch_check_finite(points, n_points * 3, flags, s))
+    return hip_fail(hipGetLastError(), "validation launch");
   if (seg::launch_resample(points, n_points, offsets, n, fibers, flags, s))
     return hip_fail(hipGetLastError(), "resample launch");
   if (validate) {
@@ -537,6 +539,7 @@ int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, 
     if (rc) return rc;
     if (f & seg::FLAG_OFFSETS)
       return fail(SEG_EOFFSETS, "a streamline is empty or its offsets leave [0, n_points]");
+    if (f & seg::FLAG_NONFINITE) return fail(SEG_ENONFINITE, "non-finite streamline coordinate");
   }
   return SEG_OK;
 }

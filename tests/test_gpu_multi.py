@@ -161,6 +161,22 @@ def test_multi_edges(seg):
         assert e.value.code == -7
 
 
+def test_multi_validation(seg):
+    import torch
+
+    fib, cen, bid, thr = pins._overlapping_set(np.random.default_rng(37), n=200, nb=4, per=3)
+    atlas = _atlas(seg, cen, bid, thr)
+    bad = fib.copy()
+    bad[17, 3, 2] = np.inf
+    log("multi validation")
+    with pytest.raises(seg.SegError) as e:
+        atlas.segment_multi(torch.from_numpy(bad).to("cuda:0"), mode="fp16", validate=True)
+    assert e.value.code == -3
+    # a valid call afterwards is unaffected
+    want = oracle.segment_multi_f32(fib, cen, bid, thr)
+    _same(_multi(seg, fib, cen, bid, thr, "fp16"), want, "after a rejected call")
+
+
 def test_multi_full_size_sampled(seg):
     """Paper-scale subject in the benchmark's configuration; the oracle
     recomputes the rows of a fixed sample of fibers."""

@@ -107,6 +107,44 @@ def test_resample_interleaved_edges(seg):
     _same(_gpu_resample(seg, pts, off), oracle.resample_f32(pts, off), "interleaved")
 
 
+def test_resample_single_points(seg):
+    """3,000 streamlines of one point each (the largest block size), and a set
+    mixing one- and two-point streamlines."""
+    rng = np.random.default_rng(15)
+    pts = rng.uniform(0, 100, (3000, 3)).astype(np.float32)
+    off = np.arange(3001, dtype=np.int64)
+    log("resample single points")
+    got = _gpu_resample(seg, pts, off)
+    assert np.array_equal(got, np.repeat(pts[:, None, :], 21, axis=1))
+    k = rng.integers(1, 3, 2000)
+    off2 = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    pts2 = rng.uniform(0, 100, (int(off2[-1]), 3)).astype(np.float32)
+    _same(_gpu_resample(seg, pts2, off2), oracle.resample_f32(pts2, off2), "one and two points")
+
+
+def test_segment_streamlines_validation(seg):
+    import torch
+
+    fib, at = synth.small_case(300, 3, 4, seed=16)
+    pts, off = synth.raw_streamlines(fib, np.random.default_rng(16))
+    d = torch.device("cuda:0")
+    _, c, b, t = to_gpu(fib[:1], at.centroids, at.bundle_id, at.thresholds)
+    atlas = seg.Atlas(c, b, t)
+    bad = off.copy()
+    bad[10] = bad[9]
+    log("segment streamlines validation")
+    with pytest.raises(seg.SegError) as e:
+        atlas.segment_streamlines(torch.from_numpy(pts).to(d), torch.from_numpy(bad).to(d),
+                                  mode="fp16", validate=True)
+    assert e.value.code == -8
+    nanpts = pts.copy()
+    nanpts[5, 1] = np.nan
+    with pytest.raises(seg.SegError) as e:
+        atlas.segment_streamlines(torch.from_numpy(nanpts).to(d), torch.from_numpy(off).to(d),
+                                  mode="fp16", validate=True)
+    assert e.value.code == -3
+
+
 def test_resample_long_lines(seg):
     """Streamlines of 500 to 3,000 points: most blocks cannot stage all of
     their points and hand the rest to the lane path."""
