@@ -43,16 +43,20 @@ struct AtlasBuf {
   float4* ccen = nullptr;   // [m_pad]
   int32_t* bid = nullptr;   // [m_pad]
   float* cext = nullptr;    // [m_pad][2]: arc length, threshold T
+  int32_t* cperm = nullptr; // [m_pad]: tile-culled centroid order (a prepared atlas)
+  bool cperm_ok = false;    // cperm holds this atlas's order
   int64_t cap = 0;          // capacity in centroids
   int64_t m = 0;
 
   int reserve(int64_t mp) {
+    cperm_ok = false;
     if (mp <= cap) return 0;
     release();
     HIP_TRY(hipMalloc(&cprep, (size_t)mp * seg::CREC_BYTES));
     HIP_TRY(hipMalloc(&ccen, (size_t)mp * sizeof(float4)));
     HIP_TRY(hipMalloc(&bid, (size_t)mp * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&cext, (size_t)mp * 2 * sizeof(float)));
+    HIP_TRY(hipMalloc(&cperm, (size_t)mp * sizeof(int32_t)));
     cap = mp;
     return 0;
   }
@@ -61,12 +65,16 @@ struct AtlasBuf {
     if (ccen) (void)hipFree(ccen);
     if (bid) (void)hipFree(bid);
     if (cext) (void)hipFree(cext);
+    if (cperm) (void)hipFree(cperm);
     cprep = nullptr;
     ccen = nullptr;
     bid = nullptr;
     cext = nullptr;
+    cperm = nullptr;
+    cperm_ok = false;
     cap = 0;
   }
+  const int32_t* order() const { return cperm_ok ? cperm : nullptr; }
 };
 
 // Per (device, stream) scratch: atlas copy for one-shot calls, flags, counters.
@@ -247,7 +255,7 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
       break;
     default:
       rc = seg::run_prefilter(o.mode, tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
-                              dists, counters, mt, sc->pre, ev, s);
+                              dists, counters, mt, sc->pre, ev, s, ab.order());
       if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
       break;
   }
@@ -357,6 +365,13 @@ int seg_atlas_create(const float* centroids, int64_t m, const int32_t* bid, cons
     return hip_fail(hipGetLastError(), "flag reset");
   }
   rc = prepare_atlas(a->buf, centroids, m, bid, thr, nb, sc->flags, s);
+  // the tile-culled centroid order depends only on the atlas: sorted once
+  // here, and complete before the handle is returned (read_flags waits)
+  if (!rc && m > 0) {
+    const int r = seg::cull_sort_centroids(a->buf.cprep, (int32_t)m, a->buf.cperm, sc->pre, s);
+    if (r == -3) rc = fail(SEG_ENOMEM, "prefilter scratch allocation failed");
+    else if (r) rc = hip_fail(hipGetLastError(), "centroid order launch");
+  }
   unsigned long long f = 0;
   if (!rc) rc = read_flags(sc->flags, s, &f);
   if (!rc) rc = flags_error(f);
@@ -365,6 +380,7 @@ int seg_atlas_create(const float* centroids, int64_t m, const int32_t* bid, cons
     delete a;
     return rc;
   }
+  a->buf.cperm_ok = m > 0;
   *out = a;
   return SEG_OK;
 }
@@ -479,7 +495,7 @@ int seg_segment_multi(const seg_atlas* a, const float* fibers, int64_t n, int32_
     const seg::MultiOut mo{slots, max_per_fiber, a->buf.bid, (unsigned int*)sc->flags};
     rc = seg::run_cull(o.mode - SEG_PREFILTER_BF16, fibers, n, a->buf.cprep, (int32_t)a->buf.m,
                        a->buf.bid, nullptr, nullptr, counters, mt, sc->pre,
-                       (hipEvent_t*)o.profile_events, s, &mo);
+                       (hipEvent_t*)o.profile_events, s, &mo, a->buf.order());
     if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
     if (rc) return hip_fail(hipGetLastError(), "kernel launch");
   }
@@ -610,7 +626,8 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
         }
         rc = seg::run_cull(o.mode - SEG_PREFILTER_BF16, fibers[i], n_fibers[i], bav[a].cprep,
                            bav[a].m, bav[a].bid, lab, dst, nullptr,
-                           seg::Metric{bav[a].cext, o.metric}, sc->pre, nullptr, s);
+                           seg::Metric{bav[a].cext, o.metric}, sc->pre, nullptr, s, nullptr,
+                           atlases[a]->buf.order());
         if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
         if (rc) return hip_fail(hipGetLastError(), "kernel launch");
       }

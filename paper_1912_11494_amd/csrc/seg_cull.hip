@@ -909,7 +909,8 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
 template <int Q>
 int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, const int32_t* bid,
                 int32_t* labels, float* dists, unsigned long long* counters, Metric mt,
-                PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo) {
+                PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo,
+                const int32_t* cperm_cached) {
   constexpr int EB = QTraits<Q>::bytes;
   const int64_t n_pad = (n + 255) / 256 * 256;
   const int32_t ncols_pad = (m + 31) / 32 * 32;
@@ -955,13 +956,15 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   cull_fiber_kernel<Q><<<(unsigned)((n + CF_BLOCK - 1) / CF_BLOCK), CF_BLOCK, 0, s>>>(
       fibers, n, prm, pay, keys_a, fkeys);
   if (radix_sort(n, keys_a, keys_b, vals_a, vals_b, hist, nullptr, nullptr, s)) return -1;
-  // centroids: cell keys, sort, then sorted columns with tile boxes
-  if (m > 0) {
+  // centroids: cell keys and sort (unless the prepared atlas holds the
+  // order), then sorted columns with tile boxes
+  if (m > 0 && !cperm_cached) {
     cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
     if (radix_sort(m, keys_a, keys_b, vals_a, cperm, hist, nullptr, nullptr, s)) return -1;
   }
   cull_column_kernel<Q><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
-      cprep, m, ncols_pad, cperm, prm, cfeat, cbias, ccent, (float*)pb.tbox);
+      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent,
+      (float*)pb.tbox);
   fill_u64_n_kernel<<<1, 64, 0, s>>>(ovf_count, 1, 0ull);
   int2* list = (int2*)pb.list;
   int2* ovf = list + nwaves * CULL_QCAP;
@@ -1000,15 +1003,35 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
 
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo) {
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo,
+             const int32_t* cperm) {
   if (n <= 0) return 0;
   if (n >= ((int64_t)1 << 31)) return -2;  // sorted rows are indexed with 32 bits
   switch (q) {
-    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
-    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
-    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo);
+    case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo, cperm);
+    case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo, cperm);
+    case 2: return cull_launch<Q_FP8>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo, cperm);
     default: return -2;
   }
+}
+
+int cull_sort_centroids(const float* cprep, int32_t m, int32_t* cperm_out, PrefilterBuf& pb,
+                        hipStream_t s) {
+  if (m <= 0) return 0;
+  const int64_t nblocks = (m + RS_IPB - 1) / RS_IPB;
+  int rc = grow(&pb.keys, &pb.keys_bytes, (size_t)m * 2 * sizeof(uint32_t));
+  rc = rc ? rc : grow(&pb.vals, &pb.vals_bytes, (size_t)m * 2 * sizeof(int32_t));
+  rc = rc ? rc : grow(&pb.hist, &pb.hist_bytes, (size_t)RS_BINS * (nblocks + 1) * 4);
+  if (rc) return rc;
+  if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
+  PfParams* prm = (PfParams*)pb.emax;
+  uint32_t* keys_a = (uint32_t*)pb.keys;
+  int32_t* vals_a = (int32_t*)pb.vals;
+  if (launch_pf_setup(prm, cprep, m, s)) return -1;
+  cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
+  if (radix_sort(m, keys_a, keys_a + m, vals_a, cperm_out, (uint32_t*)pb.hist, nullptr, nullptr, s))
+    return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace seg

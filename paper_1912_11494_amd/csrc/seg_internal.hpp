@@ -100,10 +100,12 @@ int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32
 
 // Prefilter modes (seg_prefilter.hip).  Return 0, -1 on a HIP error, -2 on an
 // unsupported mode or tile, -3 on a failed allocation.
+// `cperm`, when not null, is the atlas's sorted column order computed once by
+// cull_sort_centroids (the tile-culled form then skips that sort).
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
                   float* dists, unsigned long long* counters, Metric mt, PrefilterBuf& pb,
-                  hipEvent_t* ev, hipStream_t s);
+                  hipEvent_t* ev, hipStream_t s, const int32_t* cperm = nullptr);
 // Frame set-up shared by the prefilter forms: reset the parameters and take
 // the bounding box of the atlas points (seg_prefilter.hip).
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
@@ -111,7 +113,13 @@ int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s)
 // Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
-             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo = nullptr);
+             Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo = nullptr,
+             const int32_t* cperm = nullptr);
+// The tile-culled form's centroid order for a prepared atlas: centroids
+// sorted by the cell of their center point in the atlas's frame (the same for
+// every subject and quantisation), written to cperm_out [m].
+int cull_sort_centroids(const float* cprep, int32_t m, int32_t* cperm_out, PrefilterBuf& pb,
+                        hipStream_t s);
 
 int prefilter_pairs(int mode, const float* fibers, int64_t n, const float* cprep,
                     const float4* ccen, int32_t m, int32_t* pairs, int64_t cap,

@@ -734,12 +734,13 @@ int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s)
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
                   float* dists, unsigned long long* counters, Metric mt, PrefilterBuf& pb,
-                  hipEvent_t* ev, hipStream_t s) {
+                  hipEvent_t* ev, hipStream_t s, const int32_t* cperm) {
   (void)ccen;
   // symmetric maps: the sorted, tile-culled form unless a streaming tile is
   // asked for (or the subject is too large for 32-bit sorted rows)
   if (mode >= 2 && mode <= 4 && (cfg == CULL_TILE || (cfg == 0 && n < ((int64_t)1 << 31))))
-    return run_cull(mode - 2, fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s);
+    return run_cull(mode - 2, fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s,
+                    nullptr, cperm);
   Cfg c;
   if (resolve(mode, cfg, &c)) return -2;
   return dispatch(c, fibers, n, cprep, m, bid, labels, dists, counters, nullptr, 0, mt, pb, ev,

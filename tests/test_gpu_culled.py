@@ -155,3 +155,25 @@ def test_culled_matches_streaming(seg):
             outs.append(run(seg, fib, at.centroids, at.bundle_id, at.thresholds, mode, tile=tile))
     for lab, dist in outs[1:]:
         assert np.array_equal(lab, outs[0][0]) and np.array_equal(dist, outs[0][1])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_culled_prepared_atlas_order(seg, mode):
+    """A prepared atlas keeps its tile-culled centroid order from creation; its
+    calls equal the one-shot call, down to the culling statistics."""
+    import torch
+
+    fib, at = synth.small_case(12000, 25, 40, seed=38, len_lo=20.0, len_hi=80.0)
+    f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
+    log(f"culled prepared atlas mode={mode}")
+    l1, d1 = seg.segment(f, c, b, t, mode=mode, tile=CULL, stats=True)
+    s1 = seg.query_stats()
+    atlas = seg.Atlas(c, b, t)
+    for _ in range(2):
+        l2, d2 = atlas.segment(f, mode=mode, tile=CULL, stats=True)
+        s2 = seg.query_stats()
+        torch.cuda.synchronize()
+        assert torch.equal(l1, l2) and torch.equal(d1, d2)
+        assert s1 == s2
+    assert_parity(l2.cpu().numpy(), d2.cpu().numpy(), fib, at.centroids, at.bundle_id,
+                  at.thresholds, ctx=f"prepared {mode}", check_f64=False)
