@@ -130,8 +130,11 @@ typedef struct seg_stats {
                               prefilter bound); DENSE: pairs */
   int64_t test2_pass;      /* pairs alive after the end-point test */
   int64_t test3_pass;      /* pairs alive after the four-point test */
-  int64_t accepted;        /* pairs with D <= T2 */
-  int64_t labelled;        /* fibers with a label */
+  int64_t accepted;        /* pairs with D <= T2.  SEG_PREFILTER_BF16_ORIENTED
+                              has two columns per centroid (direct and
+                              reversed) and counts filter_pass .. accepted
+                              per surviving column, so a pair can count twice */
+  int64_t labelled;        /* -1: not collected (count labels >= 0 instead) */
   int64_t drains;          /* survivor-queue drains (wave level) */
   int64_t bound_pairs;     /* pairs the first cut evaluated one by one: N * M,
                               except for the tile-culled prefilter, which
