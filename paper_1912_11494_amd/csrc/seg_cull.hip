@@ -930,9 +930,11 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
                       (size_t)ncols_pad * (KPC * EB + 2 * sizeof(float)));
   rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes, (size_t)TROWS * ntiles * sizeof(float));
   rc = rc ? rc : grow(&pb.fkeys, &pb.fkeys_bytes, (size_t)(n + 1) * sizeof(unsigned long long));
-  // shared overflow list (its counter sits after the per-fiber keys)
-  const int64_t ovf_cap = std::min<int64_t>(std::max<int64_t>(8 * n, (int64_t)1 << 20),
-                                            (int64_t)1 << 28);
+  // shared overflow list (its counter sits after the per-fiber keys): 32
+  // entries per fiber (256 bytes, a fiber record's size), enough for the
+  // loose fp8 bound on large subjects (19 survivors per fiber at 10M x 20k)
+  const int64_t ovf_cap = std::min<int64_t>(std::max<int64_t>(32 * n, (int64_t)1 << 20),
+                                            (int64_t)1 << 30);
   rc = rc ? rc : grow(&pb.list, &pb.list_bytes,
                       (size_t)nwaves * (CULL_QCAP * sizeof(int2) + sizeof(uint32_t)) +
                           (size_t)ovf_cap * sizeof(int2));

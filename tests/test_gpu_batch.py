@@ -173,3 +173,39 @@ def test_autotune_roundtrip(seg, tmp_path):
     seg.tune_clear()
     seg.tune_load(path)
     seg.tune_clear()
+
+
+def test_batch_full_size_sampled(seg):
+    """The batch workload at full size (16 subjects, 37M fibers, two atlases) on
+    both routes; the oracle recomputes 150 fibers of every subject."""
+    import torch
+
+    wl = "batch-16-subjects-x-2-atlases"
+    atl = synth.workload_atlases(wl)
+    subs = synth.workload_subjects(wl)
+    seed = synth.workload_seed(wl)
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    rng = np.random.default_rng(39)
+    samples, gf = [], []
+    for i, sp in enumerate(subs):
+        f = synth.make_fibers(atl, sp, seed, subject_idx=i, workers=8)
+        idx = np.sort(rng.choice(len(f), 150, replace=False))
+        samples.append((idx, f[idx]))
+        gf.append(torch.from_numpy(f).to(d))
+        del f
+    log(f"batch full size: {sum(int(g.shape[0]) for g in gf)} fibers")
+    want = [[oracle.segment_f32(sf, at.centroids, at.bundle_id, at.thresholds)[:2] for at in atl]
+            for _, sf in samples]
+    for mode, tile in (("fp16", 0), ("bf16", 1)):
+        log(f"batch full size mode={mode} tile={tile}")
+        outs = seg.segment_batch(ga, gf, mode=mode, tile=tile)
+        torch.cuda.synchronize()
+        for i, (idx, _) in enumerate(samples):
+            ti = torch.from_numpy(idx).to(d)
+            for a in range(len(atl)):
+                lab = outs[i][a][0][ti].cpu().numpy()
+                dist = outs[i][a][1][ti].cpu().numpy()
+                assert np.array_equal(lab, want[i][a][0]), (mode, i, a)
+                assert np.array_equal(dist, want[i][a][1]), (mode, i, a)
+        del outs

@@ -235,7 +235,8 @@ def test_stats_and_determinism(seg):
         assert torch.equal(l2, lab) and torch.equal(d2, dist)
 
 
-@pytest.mark.parametrize("wl", ["exact-1M-x-3600", "paper-4145k-x-10k"])
+@pytest.mark.parametrize("wl", ["small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k",
+                                "large-10M-x-20k"])
 def test_full_size_sampled(seg, wl):
     """Full-size workload in the launch configuration the benchmark times;
     the oracle recomputes a fixed sample of fibers one by one."""
@@ -245,15 +246,15 @@ def test_full_size_sampled(seg, wl):
     subj = synth.workload_subjects(wl)[0]
     seed = synth.workload_seed(wl)
     log(f"full size {wl}: generating {subj.n_fibers} fibers")
-    fib = synth.make_fibers([at], subj, seed)
+    fib = synth.make_fibers([at], subj, seed, workers=8)
     f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
     rng = np.random.default_rng(len(wl))
     idx = np.sort(rng.choice(subj.n_fibers, 3000, replace=False))
     idx = np.concatenate([idx, np.arange(subj.n_fibers - 200, subj.n_fibers)])
     o32 = oracle.segment_f32(fib[idx], at.centroids, at.bundle_id, at.thresholds, mode=oracle.CUT)
     for mode in ALL_MODES:
-        if mode == "dense" and wl.startswith("paper"):
-            continue  # about 0.3 s of GPU time; covered by the 1M x 3600 case
+        if mode == "dense" and (wl.startswith("paper") or wl.startswith("large")):
+            continue  # 0.2-0.8 s of GPU time; covered by the smaller cases
         log(f"full size {wl} mode {mode}")
         lab, dist = seg.segment(f, c, b, t, mode=mode)
         torch.cuda.synchronize()
