@@ -69,18 +69,23 @@
  * Resampling (oracle_resample_f32), the step before the comparison: every
  *   subject fiber is brought to 21 points equidistant in arc length (section
  *   2.3, classification algorithm; section 2.2: the atlas centroids carry 21
- *   equidistant points).  A raw streamline is a polyline of P >= 1 points;
- *   float32 readings:
+ *   equidistant points).  A raw streamline is a polyline of P >= 1 points.
+ *   The arc length is accumulated exactly, in fixed point, so that it does
+ *   not depend on the order of summation:
  *     segment length  g_j = sqrtf of the float32 squared length of
  *                     d = fl(p_{j+1} - p_j), the same expression as the
  *                     point distance (and the arc length above);
- *     cumulative      s_0 = 0, s_{j+1} = fl(s_j + g_j), length L = s_{P-1};
- *     targets         t_k = fl(fl(k * L) / 20), k = 1..19;
- *     point k         on the first segment j with t_k <= s_{j+1}, at
- *                     w = fl(fl(t_k - s_j) / g_j) clamped to [0, 1] (0 when
- *                     g_j = 0): out = fmaf(w, fl(p_{j+1} - p_j), p_j) per
- *                     coordinate; the last point if no segment qualifies
- *                     (t_k above L by rounding);
+ *     fixed point     q_j = g_j in units of 2^-24 mm, rounded to nearest
+ *                     (ties to even); 2^38 (16.384 m) for g_j >= 2^14 mm or
+ *                     a non-finite g_j;
+ *     cumulative      S_0 = 0, S_{j+1} = S_j + q_j (exact 64-bit integers),
+ *                     L = S_{P-1};
+ *     targets         t_k = floor(k L / 20), k = 1..19 (exact);
+ *     point k         on the first segment j with t_k <= S_{j+1}, at
+ *                     w = fl(fl(t_k - S_j) / fl(q_j)) (integer differences
+ *                     converted to float32, rounded to nearest), clamped to
+ *                     [0, 1], 0 when q_j = 0: out = fmaf(w, fl(p_{j+1} -
+ *                     p_j), p_j) per coordinate;
  *     end points      out_0 = p_0 and out_20 = p_{P-1}, copied;
  *     one point       all 21 outputs are that point.
  *   A streamline without points, or offsets outside [0, npts] or decreasing,
@@ -494,34 +499,36 @@ int64_t oracle_segment_multi_f32(const float* fibers, int64_t n, const float* ce
 
 /* ---------------------------------------------------------------- resampling */
 
-/* One streamline of P >= 1 points to 21 points; s is scratch of P floats. */
-static void resample_one_f32(const float* p, int64_t P, float* s, float* out) {
-  s[0] = 0.0f;
+/* Fixed-point length of one segment (units of 2^-24 mm). */
+static int64_t seg_fixed(float g) {
+  if (!(g < 16384.0f)) return (int64_t)1 << 38;
+  return (int64_t)rintf(g * 16777216.0f);
+}
+
+/* One streamline of P >= 1 points to 21 points; S is scratch of P sums. */
+static void resample_one_f32(const float* p, int64_t P, int64_t* S, float* out) {
+  S[0] = 0;
   for (int64_t j = 0; j + 1 < P; ++j) {
     float dx = p[3 * (j + 1)] - p[3 * j];
     float dy = p[3 * (j + 1) + 1] - p[3 * j + 1];
     float dz = p[3 * (j + 1) + 2] - p[3 * j + 2];
-    s[j + 1] = s[j] + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    S[j + 1] = S[j] + seg_fixed(sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))));
   }
-  float L = s[P - 1];
+  int64_t L = S[P - 1];
   for (int c = 0; c < 3; ++c) {
     out[c] = p[c];
     out[3 * (NP - 1) + c] = p[3 * (P - 1) + c];
   }
   for (int k = 1; k < NP - 1; ++k) {
-    float t = ((float)k * L) / 20.0f;
+    int64_t t = (L / 20) * k + ((L % 20) * k) / 20;
     int64_t j = 0;
-    while (j + 1 < P && !(t <= s[j + 1])) ++j;
-    if (j + 1 >= P) {  /* no segment reaches t (or a single point) */
+    while (j + 1 < P && !(t <= S[j + 1])) ++j;
+    if (j + 1 >= P) {  /* a single point */
       for (int c = 0; c < 3; ++c) out[3 * k + c] = p[3 * (P - 1) + c];
       continue;
     }
-    /* the segment's own length, not the difference of the rounded sums */
-    float dx = p[3 * (j + 1)] - p[3 * j];
-    float dy = p[3 * (j + 1) + 1] - p[3 * j + 1];
-    float dz = p[3 * (j + 1) + 2] - p[3 * j + 2];
-    float g = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-    float w = g > 0.0f ? (t - s[j]) / g : 0.0f;
+    int64_t q = S[j + 1] - S[j];
+    float w = q > 0 ? (float)(t - S[j]) / (float)q : 0.0f;
     w = w < 0.0f ? 0.0f : (w > 1.0f ? 1.0f : w);
     for (int c = 0; c < 3; ++c) {
       float a = p[3 * j + c], b = p[3 * (j + 1) + c];
@@ -543,7 +550,7 @@ int oracle_resample_f32(const float* pts, const int64_t* off, int64_t n, int64_t
 #pragma omp parallel
 #endif
   {
-    float* s = (float*)malloc((size_t)pmax * sizeof(float));
+    int64_t* s = (int64_t*)malloc((size_t)pmax * sizeof(int64_t));
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 256)
 #endif

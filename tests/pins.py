@@ -581,21 +581,38 @@ def pin_resample_invariants(O, seed=17):
 
 
 def pin_resample_rounding_corners(O):
-    """Two float32 corners, worked by hand from the stated reading.
-    (a) Along x: 0, 2^25, 1, 2^26.  fl(1 - 2^25) = -2^25 (a tie, to even), so the
-        lengths are 2^25, 2^25, 2^26, L = 2^27 and t_10 = 2^26 = s_2: the first
-        segment reaching t_10 is the second, at w = 1, and fl(2^25 + fl(1 - 2^25))
-        puts point 10 at x = 0, not at the third input point (x = 1).
-    (b) (0,0,0), (2^24,0,0), (2^24,1.5,0), (2^24,1.5,2^24+2): lengths 2^24, 1.5,
-        2^24+2; s_2 = fl(2^24 + 1.5) = 2^24 + 2, L = 2^25 + 4, t_10 = 2^24 + 2
-        (fl(10 L) = 335544352), so w = 2 / 1.5 is clamped to 1: point 10 is the
-        third input point; t_5 = 8388609 gives (8388609, 0, 0)."""
-    a = np.array([[0.0, 0, 0], [2.0**25, 0, 0], [1.0, 0, 0], [2.0**26, 0, 0]])
-    b = np.array([[0.0, 0, 0], [2.0**24, 0, 0], [2.0**24, 1.5, 0], [2.0**24, 1.5, 2.0**24 + 2]])
-    out = O.resample_f32(*_csr([a, b]))
+    """Corners of the fixed-point reading, worked by hand (lengths in units of
+    u = 2^-24 mm).
+    (a) A tie.  Along x: 0, 4096, 2^-13, 8192.  fl(2^-13 - 4096) = -4096 (a
+        tie, to even) and fl(8192 - 2^-13) = 8192, so the lengths are 2^36,
+        2^36, 2^37 u, L = 2^38 and t_10 = 2^37 = S_2: the first segment
+        reaching t_10 is the second, at w = 1, and fma(1, -4096, 4096) puts
+        point 10 at x = 0, not at the third input point (x = 2^-13).
+    (b) Saturation.  Along x: 0, 20000, 60000: both lengths are at least 2^14
+        mm and count 2^38 u each, L = 2^39; t_10 = S_1 is the end of the first
+        segment (x = 20000) and t_5 its middle (x = 10000).  Unsaturated
+        lengths would put them at 30000 and 15000.
+    (c) Exact sums.  (0,0,0), (4096,0,0), then 4096 steps of 2^-12 mm along y:
+        L = 2^36 + 2^24 u (4097 mm) exactly, t_10 = L / 2, w = 1/2 + 2^-13, so
+        point 10 is (2048.5, 0, 0).  A float32 running sum stays at 4096
+        (4096 + 2^-12 is a tie, to even) and would give 2048.
+    (d) Floored targets.  Along x: 0, 10 u, 19 u: L = 19 u, t_10 = floor(9.5)
+        = 9 on the first segment at w = fl(9/10), so point 10 is at 9 u (fl(fl(0.9)
+        * 10) = 9); a rounded target (10) would give 10 u."""
+    u = 2.0**-24
+    a = np.array([[0.0, 0, 0], [4096.0, 0, 0], [2.0**-13, 0, 0], [8192.0, 0, 0]])
+    b = np.array([[0.0, 0, 0], [20000.0, 0, 0], [60000.0, 0, 0]])
+    c = np.zeros((4098, 3))
+    c[1:, 0] = 4096.0
+    c[2:, 1] = np.arange(1, 4097) * 2.0**-12
+    d = np.array([[0.0, 0, 0], [10 * u, 0, 0], [19 * u, 0, 0]])
+    out = O.resample_f32(*_csr([a, b, c, d]))
     assert np.array_equal(out[0][10], np.array([0.0, 0.0, 0.0], F32)), out[0][10]
-    assert np.array_equal(out[1][10], b[2].astype(F32)), out[1][10]
-    assert np.array_equal(out[1][5], np.array([8388609.0, 0.0, 0.0], F32)), out[1][5]
+    assert np.array_equal(out[1][10], np.array([20000.0, 0.0, 0.0], F32)), out[1][10]
+    assert np.array_equal(out[1][5], np.array([10000.0, 0.0, 0.0], F32)), out[1][5]
+    assert np.array_equal(out[2][10], np.array([2048.5, 0.0, 0.0], F32)), out[2][10]
+    assert np.array_equal(out[2][20], np.array([4096.0, 1.0, 0.0], F32)), out[2][20]
+    assert np.array_equal(out[3][10], np.array([9 * u, 0.0, 0.0], F32)), out[3][10]
 
 
 # ---------------------------------------------------------------- several labels

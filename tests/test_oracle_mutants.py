@@ -61,17 +61,24 @@ MUTANTS = {
     "multi_counts_set_not_added": ("bundle_counts[bundles[i]] += 1;", "bundle_counts[bundles[i]] = 1;"),
     "multi_threshold_of_bundle_zero": ("    float tt = t2[bid[c]];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k",
                                        "    float tt = t2[0];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k"),
-    "resample_k_over_21": ("float t = ((float)k * L) / 20.0f;", "float t = ((float)k * L) / 21.0f;"),
-    "resample_strict_tie": ("while (j + 1 < P && !(t <= s[j + 1])) ++j;",
-                            "while (j + 1 < P && !(t < s[j + 1])) ++j;"),
-    "resample_no_clamp": ("w = w < 0.0f ? 0.0f : (w > 1.0f ? 1.0f : w);", "w = w < 0.0f ? 0.0f : w;"),
+    "resample_k_over_21": ("int64_t t = (L / 20) * k + ((L % 20) * k) / 20;",
+                           "int64_t t = (L / 21) * k + ((L % 21) * k) / 21;"),
+    "resample_target_rounded": ("int64_t t = (L / 20) * k + ((L % 20) * k) / 20;",
+                                "int64_t t = (L / 20) * k + ((L % 20) * k + 10) / 20;"),
+    "resample_strict_tie": ("while (j + 1 < P && !(t <= S[j + 1])) ++j;",
+                            "while (j + 1 < P && !(t < S[j + 1])) ++j;"),
+    "resample_no_saturation": ("if (!(g < 16384.0f)) return (int64_t)1 << 38;",
+                               "if (!(g < 1e9f)) return (int64_t)1 << 38;"),
+    "resample_float_accumulation": (
+        "S[j + 1] = S[j] + seg_fixed(sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))));",
+        "S[j + 1] = seg_fixed((float)S[j] / 16777216.0f + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))));"),
     "resample_from_far_end": ("out[3 * k + c] = fmaf(w, b - a, a);", "out[3 * k + c] = fmaf(w, a - b, b);"),
-    "resample_by_index": ("s[j + 1] = s[j] + sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));",
-                          "s[j + 1] = s[j] + 1.0f;"),
+    "resample_by_index": ("S[j + 1] = S[j] + seg_fixed(sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))));",
+                          "S[j + 1] = S[j] + 16777216;"),
     "resample_last_point_off_by_one": ("out[3 * (NP - 1) + c] = p[3 * (P - 1) + c];",
                                        "out[3 * (NP - 1) + c] = p[3 * (P > 1 ? P - 2 : 0) + c];"),
     "resample_skips_first_segment": ("for (int64_t j = 0; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];",
-                                     "s[1] = 0.0f;\n  for (int64_t j = 1; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];"),
+                                     "S[1] = 0;\n  for (int64_t j = 1; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];"),
     "resample_accepts_empty": ("off[i + 1] <= off[i]) return -2;", "off[i + 1] < off[i]) return -2;"),
 }
 
