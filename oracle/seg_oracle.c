@@ -88,8 +88,9 @@
  *                     p_j), p_j) per coordinate;
  *     end points      out_0 = p_0 and out_20 = p_{P-1}, copied;
  *     one point       all 21 outputs are that point.
- *   A streamline without points, or offsets outside [0, npts] or decreasing,
- *   is an error.
+ *   A streamline without points or of more than 2^24 points (so that its
+ *   sum stays below 2^62), or offsets outside [0, npts] or decreasing, is an
+ *   error.
  * Precisions:
  *   *_f32  the float32 decision above (labels must match it bit for bit);
  *   *_f64  the same definition in double precision with exact differences,
@@ -543,6 +544,7 @@ int oracle_resample_f32(const float* pts, const int64_t* off, int64_t n, int64_t
   int64_t pmax = 1;
   for (int64_t i = 0; i < n; ++i) {
     if (off[i] < 0 || off[i + 1] > npts || off[i + 1] <= off[i]) return -2;
+    if (off[i + 1] - off[i] > ((int64_t)1 << 24)) return -2;
     if (off[i + 1] - off[i] > pmax) pmax = off[i + 1] - off[i];
   }
 #ifdef _OPENMP

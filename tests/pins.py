@@ -11,6 +11,7 @@ each plausible mistake is caught by at least one of them.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -556,6 +557,15 @@ def pin_resample_vs_interp(O, seed=16):
         assert np.array_equal(o[[0, 20]], p[[0, -1]])
 
 
+@functools.lru_cache(maxsize=1)
+def _long_line():
+    """2^24 + 1 points 0.25 mm apart along x (exact in float32)."""
+    big = np.zeros((2**24 + 1, 3), F32)
+    big[:, 0] = np.arange(2**24 + 1, dtype=F32) * F32(0.25)
+    big.setflags(write=False)
+    return big
+
+
 def pin_resample_invariants(O, seed=17):
     """Repeating points (zero-length steps) changes nothing, bit for bit; a set
     gives each streamline's own result; reversal gives the reversed points
@@ -578,6 +588,16 @@ def pin_resample_invariants(O, seed=17):
         except ValueError:
             continue
         raise AssertionError(f"offsets {bad} accepted")
+    # at most 2^24 points per streamline: the exact sum stays below 2^62
+    big = _long_line()
+    one = O.resample_f32(big[:2**24], np.array([0, 2**24], np.int64))[0]
+    assert one[10, 0] == F32(0.25 * (2**24 - 1) / 2) and one[20, 0] == big[2**24 - 1, 0]
+    try:
+        O.resample_f32(big, np.array([0, 2**24 + 1], np.int64))
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a streamline of 2^24 + 1 points accepted")
 
 
 def pin_resample_rounding_corners(O):

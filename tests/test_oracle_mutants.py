@@ -79,6 +79,7 @@ MUTANTS = {
                                        "out[3 * (NP - 1) + c] = p[3 * (P > 1 ? P - 2 : 0) + c];"),
     "resample_skips_first_segment": ("for (int64_t j = 0; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];",
                                      "S[1] = 0;\n  for (int64_t j = 1; j + 1 < P; ++j) {\n    float dx = p[3 * (j + 1)] - p[3 * j];"),
+    "resample_accepts_long": ("if (off[i + 1] - off[i] > ((int64_t)1 << 24)) return -2;", ""),
     "resample_accepts_empty": ("off[i + 1] <= off[i]) return -2;", "off[i + 1] < off[i]) return -2;"),
 }
 
