@@ -288,19 +288,21 @@ int seg_segment_multi(const seg_atlas* atlas, const float* fibers, int64_t n,
  * fibers   device output, [n][21][3] float32 (the fiber layout of
  *          seg_segment), caller-owned.
  *
- * Arithmetic (float32, fixed so results are reproducible bit for bit):
- *   segment j:  d = p[j+1] - p[j], g_j = sqrtf(fma(dz, dz, fma(dy, dy, dx*dx)));
- *   s_0 = 0, s_{j+1} = s_j + g_j summed in point order, L = s_{P-1};
- *   targets t_k = (k * L) / 20, k = 1..19, each rounded once;
- *   point k lies on the first segment j with t_k <= s_{j+1}, at weight
- *   w = (t_k - s_j) / g_j clamped to [0, 1] (0 when g_j = 0):
- *   out_k = fma(w, d, p[j]) per coordinate; a target above every s (by
- *   rounding) takes the last point; out_0 = p[0], out_20 = p[P-1] exactly;
- *   a single point gives 21 copies of it.
- * A streamline with no points, or whose offsets leave [0, n_points] or
- * decrease, gets 21 NaN points and no read of `points`; with validate = 1
- * the call synchronises the stream and returns SEG_EOFFSETS for it, or
- * SEG_ENONFINITE for a NaN / inf coordinate among the n_points points.
+ * Arithmetic (fixed so results are reproducible bit for bit):
+ *   segment j:  d = p[j+1] - p[j] and g_j = sqrtf(fma(dz, dz, fma(dy, dy,
+ *   dx*dx))) in float32; q_j = g_j in units of 2^-24 mm rounded to nearest
+ *   even, or 2^38 when g_j >= 2^14 mm or is not finite;
+ *   S_0 = 0, S_{j+1} = S_j + q_j summed exactly in 64-bit integers, L = S_{P-1};
+ *   targets t_k = floor(k L / 20), k = 1..19;
+ *   point k lies on the first segment j with t_k <= S_{j+1}, at weight
+ *   w = (float)(t_k - S_j) / (float)q_j clamped to [0, 1] (0 when q_j = 0):
+ *   out_k = fma(w, d, p[j]) per coordinate; out_0 = p[0], out_20 = p[P-1]
+ *   exactly; a single point gives 21 copies of it.
+ * A streamline with no points or more than 2^24 points, or whose offsets
+ * leave [0, n_points] or decrease, gets 21 NaN points and no read of
+ * `points`; with validate = 1 the call synchronises the stream and returns
+ * SEG_EOFFSETS for it, or SEG_ENONFINITE for a NaN / inf coordinate among
+ * the n_points points.
  * n = 0 returns SEG_OK without launching.
  */
 int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, int64_t n,

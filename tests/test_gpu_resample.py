@@ -48,15 +48,25 @@ def _same(a, b, ctx):
     assert bad.size == 0, f"{ctx}: {bad.size} streamlines differ, first {bad[:5]}"
 
 
+def _corner_lines():
+    """The four hand-worked corners of the fixed-point reading: a rounding
+    tie, saturated lengths, a sum a float32 running total would lose, a
+    floored target (expected points in test_resample_edges)."""
+    u = 2.0**-24
+    c = np.zeros((4098, 3))
+    c[1:, 0] = 4096.0
+    c[2:, 1] = np.arange(1, 4097) * 2.0**-12
+    return [np.array([[0.0, 0, 0], [4096.0, 0, 0], [2.0**-13, 0, 0], [8192.0, 0, 0]]),
+            np.array([[0.0, 0, 0], [20000.0, 0, 0], [60000.0, 0, 0]]), c,
+            np.array([[0.0, 0, 0], [10 * u, 0, 0], [19 * u, 0, 0]])]
+
+
 def _edge_lines():
-    """Single points, two points, zero-length lines, repeated points, the two
-    hand-worked float32 rounding corners, a 5,000-point line."""
+    """Single points, two points, zero-length lines, the fixed-point corners,
+    repeated points, a 5,000-point line (longer than a wave's LDS slice)."""
     rng = np.random.default_rng(5)
     lines = [np.array([[5.0, 6.0, 7.0]]), np.array([[1.0, 2.0, 3.0], [4.0, 8.0, 12.0]]),
-             np.repeat(np.array([[9.0, 9.0, 9.0]]), 50, 0),
-             np.array([[0.0, 0, 0], [2.0**25, 0, 0], [1.0, 0, 0], [2.0**26, 0, 0]]),
-             np.array([[0.0, 0, 0], [2.0**24, 0, 0], [2.0**24, 1.5, 0],
-                       [2.0**24, 1.5, 2.0**24 + 2]])]
+             np.repeat(np.array([[9.0, 9.0, 9.0]]), 50, 0)] + _corner_lines()
     c = pins._raw_curve(rng, 300, 60.0, (50.0, 60.0, 70.0))
     lines.append(np.repeat(c, rng.integers(1, 4, len(c)), axis=0))
     lines.append(pins._raw_curve(rng, 5000, 180.0, (10.0, 20.0, 10.0)))
@@ -89,8 +99,12 @@ def test_resample_edges(seg):
     log(f"resample edges {len(lines)} lines")
     got = _gpu_resample(seg, pts, off)
     _same(got, oracle.resample_f32(pts, off), "edges")
-    assert np.array_equal(got[3][10], np.zeros(3, np.float32))
-    assert np.array_equal(got[4][10], np.array([2.0**24, 1.5, 0.0], np.float32))
+    f32 = np.float32
+    assert np.array_equal(got[3][10], np.zeros(3, f32))
+    assert np.array_equal(got[4][10], np.array([20000.0, 0, 0], f32))
+    assert np.array_equal(got[4][5], np.array([10000.0, 0, 0], f32))
+    assert np.array_equal(got[5][10], np.array([2048.5, 0, 0], f32))
+    assert np.array_equal(got[6][10], np.array([9 * 2.0**-24, 0, 0], f32))
 
 
 def test_resample_interleaved_edges(seg):
@@ -108,8 +122,8 @@ def test_resample_interleaved_edges(seg):
 
 
 def test_resample_single_points(seg):
-    """3,000 streamlines of one point each (the largest block size), and a set
-    mixing one- and two-point streamlines."""
+    """3,000 streamlines of one point each, and a set mixing one- and
+    two-point streamlines."""
     rng = np.random.default_rng(15)
     pts = rng.uniform(0, 100, (3000, 3)).astype(np.float32)
     off = np.arange(3001, dtype=np.int64)
@@ -146,11 +160,15 @@ def test_segment_streamlines_validation(seg):
 
 
 def test_resample_long_lines(seg):
-    """Streamlines of 500 to 3,000 points: most blocks cannot stage all of
-    their points and hand the rest to the lane path."""
+    """Streamlines of 500 to 3,000 points: those of more than 640 segments
+    take the one-lane path, the others the wave path; and segment counts
+    around a chunk of 64, a round of four chunks and the slice of 640."""
     rng = np.random.default_rng(13)
-    lines = [pins._raw_curve(rng, int(rng.integers(500, 3000)), rng.uniform(100, 250),
-                             rng.uniform([20, 20, 20], [60, 60, 60])) for _ in range(300)]
+    sizes = [int(x) for x in rng.integers(500, 3000, 300)]
+    sizes += [2, 3, 63, 64, 65, 66, 127, 128, 129, 256, 257, 258, 512, 513, 639, 640, 641, 642,
+              643, 1025, 2049]
+    lines = [pins._raw_curve(rng, k, rng.uniform(100, 250), rng.uniform([20, 20, 20], [60, 60, 60]))
+             for k in sizes]
     pts, off = pins._csr(lines)
     log(f"resample long lines: {pts.shape[0]} points")
     _same(_gpu_resample(seg, pts, off), oracle.resample_f32(pts, off), "long lines")
@@ -192,9 +210,20 @@ def test_resample_bad_offsets(seg):
     with pytest.raises(seg.SegError) as e:
         _gpu_resample(seg, pts, bad, validate=True)
     assert e.value.code == -8
+    # more than 2^24 points in one streamline: NaN, and SEG_EOFFSETS on validation
+    d = torch.device("cuda:0")
+    gbig = torch.zeros((2**24 + 2, 3), dtype=torch.float32, device=d)
+    for o2 in ([0, 2**24 + 1], [0, 1, 2**24 + 2]):
+        got2 = seg.resample(gbig, torch.tensor(o2, dtype=torch.int64, device=d)).cpu().numpy()
+        assert np.isnan(got2[-1]).all()
+        if len(o2) == 3:
+            assert np.array_equal(got2[0], np.zeros((21, 3), np.float32))
+        with pytest.raises(seg.SegError) as e:
+            seg.resample(gbig, torch.tensor(o2, dtype=torch.int64, device=d), validate=True)
+        assert e.value.code == -8
+    del gbig
     # valid offsets pass validation
     _same(_gpu_resample(seg, pts, off, validate=True), want, "validated")
-    d = torch.device("cuda:0")
     empty = seg.resample(torch.zeros((0, 3), dtype=torch.float32, device=d),
                          torch.zeros(1, dtype=torch.int64, device=d))
     assert empty.shape == (0, 21, 3)
