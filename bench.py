@@ -160,8 +160,8 @@ def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
                                    "the byte value of one counted KiB"}}
     for prefix, key in TRAFFIC_KERNELS:
         # the launch that bench.py times: statistics off (template flag false)
-        ks = [k for k in fe if k.replace(" ", "").startswith("void" + prefix.replace(" ", ""))
-              and "true" not in k]
+        ks = [k for k in fe if k.replace(" ", "").removeprefix("void").startswith(
+              prefix.replace(" ", "")) and "true" not in k]
         if not ks:
             continue
         k = ks[0]
@@ -380,7 +380,7 @@ def bench_resample(P, hip, f, at, c, b, t, wl, head, args, N, np):
         res["cpu_baseline"] = {"value": ns / dt, "unit": "streamlines/s", "cores": thr,
                                "kind": "oracle",
                                "sample": f"all {ns:,} of {N:,} streamlines "
-                                         f"({int(off_h[-1]):,} points), float32, OpenMP {thr} "
+                                         f"({int(off_h[-1]):,} points), fixed-point arc length, OpenMP {thr} "
                                          f"threads; {dt:.2f} s"}
         res["sample_mismatches_vs_oracle"] = int((~((got == want) | (np.isnan(got) &
                                                    np.isnan(want)))).any(axis=(1, 2)).sum())
