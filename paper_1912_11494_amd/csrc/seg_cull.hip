@@ -40,6 +40,7 @@
 #include <type_traits>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "seg_device.hpp"
@@ -278,13 +279,29 @@ __global__ __launch_bounds__(256) void cell_key_kernel(const float* __restrict__
 // and error bound +inf (its box is unbounded).
 constexpr int PAY_WORDS = 4;
 
-// One lane per fiber: a block of CF_BLOCK fibers copies its contiguous
-// records (CF_BLOCK x 252 bytes) into LDS with coalesced 16-byte loads, then
-// each lane quantises its own record from LDS (a stride of 63 words, no bank
-// conflict) and writes its payload, its center-cell key and the reset value
-// of its argmin key.
+// One lane per fiber: a block takes batches of CF_BLOCK fibers (grid-stride,
+// as many blocks as the device holds at once);
+// a batch's contiguous records (CF_BLOCK x 252 bytes) come in with coalesced
+// 16-byte loads into registers, go to LDS, and the loads of the block's next
+// batch are issued before the lanes quantise the current one, each its own
+// record from LDS (a stride of 63 words, no bank conflict), and write its
+// payload, its center-cell key and the reset value of its argmin key.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 constexpr int CF_BLOCK = 128;
+constexpr int CF_V = (CF_BLOCK * NF / 4 + CF_BLOCK - 1) / CF_BLOCK;  // loads per lane
+
+__device__ __forceinline__ void cf_load(const float* __restrict__ fibers, int64_t n, int64_t b,
+                                        int tid, f4u* v) {
+  const int64_t f0 = b * CF_BLOCK;
+  const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
+  const int n4 = (cnt * NF) >> 2;
+  const float* __restrict__ src = fibers + f0 * NF;
+#pragma unroll
+  for (int u = 0; u < CF_V; ++u) {
+    const int i = tid + u * CF_BLOCK;
+    if (i < n4) v[u] = *(const f4u*)(src + 4 * i);
+  }
+}
 
 template <int Q>
 __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __restrict__ fibers,
@@ -295,53 +312,82 @@ __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __res
                                                               unsigned long long* __restrict__ fkeys) {
   __shared__ float s_rec[CF_BLOCK * NF];
   const int tid = (int)threadIdx.x;
-  const int64_t f0 = (int64_t)blockIdx.x * CF_BLOCK;
-  const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
-  {
-    const float* __restrict__ src = fibers + f0 * NF;
-    const int nfl = cnt * NF;
-    const int n4 = nfl >> 2;
-#pragma unroll 4
-    for (int i = tid; i < n4; i += CF_BLOCK) {
-      const f4u v = *(const f4u*)(src + 4 * i);
-      s_rec[4 * i] = v.x;
-      s_rec[4 * i + 1] = v.y;
-      s_rec[4 * i + 2] = v.z;
-      s_rec[4 * i + 3] = v.w;
-    }
-    if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = src[4 * n4 + tid];
-  }
-  __syncthreads();
-  const int64_t f = f0 + tid;
+  const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK;
+  f4u v[CF_V];
+  int64_t b = blockIdx.x;
+  if (b < nb) cf_load(fibers, n, b, tid, v);
   float e32 = 0.0f;
-  if (tid < cnt) {
-    float rec[NF];
+  for (; b < nb; b += gridDim.x) {
+    const int64_t f0 = b * CF_BLOCK;
+    const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
+    {
+      const int nfl = cnt * NF;
+      const int n4 = nfl >> 2;
 #pragma unroll
-    for (int k = 0; k < NF; ++k) rec[k] = s_rec[tid * NF + k];
-    uint4* P = pay + f * PAY_WORDS;
-    if (QTraits<Q>::bytes == 1) P[1] = make_uint4(0u, 0u, 0u, 0u);
-    double nq, e;
-    quantise_row<Q, MAP_SYM, KPC>(rec, false, prm, (uint8_t*)P, &nq, &e);
-    float nh, er;
-    if (!__builtin_isfinite(e)) {
-      nh = __builtin_inff();
-      er = __builtin_inff();
-    } else {
-      const double g = gamma_acc(KPC);
-      const double ha = (0.5 - g) * nq * (1.0 - 0x1p-40);  // round towards passing
-      nh = __double2float_ru(-ha * frame(prm, Q).s2);
-      er = __double2float_ru(e);
-      e32 = er;
+      for (int u = 0; u < CF_V; ++u) {
+        const int i = tid + u * CF_BLOCK;
+        if (i < n4) {
+          s_rec[4 * i] = v[u].x;
+          s_rec[4 * i + 1] = v[u].y;
+          s_rec[4 * i + 2] = v[u].z;
+          s_rec[4 * i + 3] = v[u].w;
+        }
+      }
+      if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = fibers[f0 * NF + 4 * n4 + tid];
     }
-    P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)f, 0u);
-    P[3] = make_uint4(0u, 0u, 0u, 0u);
-    keys[f] = center_cell(rec, prm);
-    fkeys[f] = NO_KEY;
+    __syncthreads();
+    if (b + gridDim.x < nb) cf_load(fibers, n, b + gridDim.x, tid, v);
+    const int64_t f = f0 + tid;
+    if (tid < cnt) {
+      float rec[NF];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) rec[k] = s_rec[tid * NF + k];
+      uint4* P = pay + f * PAY_WORDS;
+      if (QTraits<Q>::bytes == 1) P[1] = make_uint4(0u, 0u, 0u, 0u);
+      double nq, e;
+      quantise_row<Q, MAP_SYM, KPC>(rec, false, prm, (uint8_t*)P, &nq, &e);
+      float nh, er;
+      if (!__builtin_isfinite(e)) {
+        nh = __builtin_inff();
+        er = __builtin_inff();
+      } else {
+        const double g = gamma_acc(KPC);
+        const double ha = (0.5 - g) * nq * (1.0 - 0x1p-40);  // round towards passing
+        nh = __double2float_ru(-ha * frame(prm, Q).s2);
+        er = __double2float_ru(e);
+        e32 = fmaxf(e32, er);
+      }
+      P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)f, 0u);
+      P[3] = make_uint4(0u, 0u, 0u, 0u);
+      keys[f] = center_cell(rec, prm);
+      fkeys[f] = NO_KEY;
+    }
+    __syncthreads();  // the records are read before the next batch lands
   }
   for (int off = 32; off > 0; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off));
   if ((tid & 63) == 0)
     atomicMax(&prm->emax_bits[(blockIdx.x * (CF_BLOCK / 64) + (tid >> 6)) % EMAX_SLOTS],
               __float_as_uint(e32));
+}
+
+// Blocks of cull_fiber_kernel<Q> that the device holds at once (register- or
+// LDS-bound), queried once per process and quantisation.
+template <int Q>
+int64_t cf_grid() {
+  static std::atomic<int64_t> g{0};
+  int64_t v = g.load(std::memory_order_relaxed);
+  if (v == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cull_fiber_kernel<Q>, CF_BLOCK, 0) !=
+            hipSuccess ||
+        cus <= 0 || per <= 0)
+      return 1024;
+    v = (int64_t)cus * per;
+    g.store(v, std::memory_order_relaxed);
+  }
+  return v;
 }
 
 // Lowest / highest over the 32 lanes of each half wave.
@@ -955,8 +1001,11 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   // fibers: payloads and cell keys in input order, then the sort
   unsigned long long* fkeys = (unsigned long long*)pb.fkeys;
   unsigned long long* ovf_count = fkeys + n;
-  cull_fiber_kernel<Q><<<(unsigned)((n + CF_BLOCK - 1) / CF_BLOCK), CF_BLOCK, 0, s>>>(
-      fibers, n, prm, pay, keys_a, fkeys);
+  {
+    const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK, g = cf_grid<Q>();
+    cull_fiber_kernel<Q><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(fibers, n, prm, pay,
+                                                                          keys_a, fkeys);
+  }
   if (radix_sort(n, keys_a, keys_b, vals_a, vals_b, hist, nullptr, nullptr, s)) return -1;
   // centroids: cell keys and sort (unless the prepared atlas holds the
   // order), then sorted columns with tile boxes
