@@ -380,8 +380,8 @@ def bench_resample(P, hip, f, at, c, b, t, wl, head, args, N, np):
         res["cpu_baseline"] = {"value": ns / dt, "unit": "streamlines/s", "cores": thr,
                                "kind": "oracle",
                                "sample": f"all {ns:,} of {N:,} streamlines "
-                                         f"({int(off_h[-1]):,} points), fixed-point arc length, OpenMP {thr} "
-                                         f"threads; {dt:.2f} s"}
+                                         f"({int(off_h[-1]):,} points), fixed-point arc "
+                                         f"length, OpenMP {thr} threads; {dt:.2f} s"}
         res["sample_mismatches_vs_oracle"] = int((~((got == want) | (np.isnan(got) &
                                                    np.isnan(want)))).any(axis=(1, 2)).sum())
     del pts, off
