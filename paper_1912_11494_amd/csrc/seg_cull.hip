@@ -519,6 +519,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
                                                          const unsigned long long* __restrict__ ovf_count,
                                                          int64_t ovf_cap,
                                                          const int32_t* __restrict__ perm,
+                                                         int64_t n,
                                                          const float* __restrict__ fibers,
                                                          const float* __restrict__ cprep,
                                                          unsigned long long* __restrict__ keys,
@@ -528,15 +529,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves) return;
   const int lane = (int)(threadIdx.x & 63);
+  // the input indices of the wave's 64 sorted rows, read up front: the rows
+  // of its own list lie in this window
+  const int64_t prow = w * 64 + lane;
+  const int32_t pwin = perm[prow < n ? prow : n - 1];
   // 64 pairs per step, one per lane.  An entry is (sorted row, centroid);
   // row -1 marks an unused entry, and the rows of a rescued wave are left to
   // the rescue kernel.
-  auto run = [&](const int2* __restrict__ src, int64_t cnt) {
+  // `own`: the wave's own list, whose rows are all the wave's own (its flag
+  // was tested already); the overflow list mixes rows of every wave
+  // `first`: the entry of this lane in the first 64, when read already
+  auto run = [&](const int2* __restrict__ src, int64_t cnt, bool own, const int2* first) {
     for (int64_t j0 = 0; j0 < cnt; j0 += 64) {
       const int64_t j = j0 + lane;
-      int2 e = j < cnt ? src[j] : make_int2(-1, 0);
-      bool act = e.x >= 0 && !(list_n[e.x >> 6] & RESCUE);
-      e = act ? make_int2(perm[e.x], e.y) : make_int2(0, 0);
+      const bool pre = j0 == 0 && first;  // the same on every lane
+      int2 e = j < cnt ? (pre ? *first : src[j]) : make_int2(-1, 0);
+      bool act = e.x >= 0 && (own || !(list_n[e.x >> 6] & RESCUE));
+      int32_t fi;
+      if (pre)
+        fi = __shfl(pwin, (int)(e.x - w * 64) & 63);  // every lane takes part
+      else
+        fi = act ? perm[e.x] : 0;
+      e = act ? make_int2(fi, e.y) : make_int2(0, 0);
       const float* ar = fibers + (int64_t)e.x * NF;
       const float* br = cprep + (size_t)e.y * CREC;
       float D, v;
@@ -574,12 +588,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
       }
     }
   };
+  // the wave's first 64 entries are read with its count, not after it (the
+  // wave's part of the list always exists; entries past the count are unused)
+  const int2 first = list[w * QCAP + lane];
   const uint32_t cnt = list_n[w];
-  if (!(cnt & RESCUE)) run(list + w * QCAP, cnt);  // a rescued wave: the rescue kernel
+  if (!(cnt & RESCUE)) run(list + w * QCAP, cnt, true, &first);  // else: the rescue kernel
   // the shared overflow list, 64 entries per wave in turn
   const int64_t total = (int64_t)*ovf_count < ovf_cap ? (int64_t)*ovf_count : ovf_cap;
   for (int64_t i0 = w * 64; i0 < total; i0 += nwaves * 64)
-    run(ovf + i0, total - i0 < 64 ? total - i0 : 64);
+    run(ovf + i0, total - i0 < 64 ? total - i0 : 64, false, nullptr);
 }
 
 // Waves of the culled kernel whose survivors overflowed: each lane takes one
@@ -1033,8 +1050,8 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   auto exact = [&](auto stats, auto multi) {
     constexpr bool ST = decltype(stats)::value, MU = decltype(multi)::value;
     exact_list_kernel<ST, CULL_QCAP, MU><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, fibers, cprep, fkeys, counters, mt,
-        mout);
+        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, n, fibers, cprep, fkeys, counters,
+        mt, mout);
     rescue_kernel<ST, MU><<<blocks < 1024u ? blocks : 1024u, 256, 0, s>>>(
         list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys, counters, mt, mout);
   };
