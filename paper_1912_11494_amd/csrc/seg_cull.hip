@@ -697,18 +697,35 @@ __global__ __launch_bounds__(256) void cull_kernel(CullJob job,
   // -Ha of the wave's 64 rows: the MFMA C operand, read when a product runs
   __shared__ __attribute__((aligned(16))) float s_nh[WAVES][FPW];
   const double is = frame(job.prm, Q).is;
+  // both groups' permutation entries, then both groups' payloads, in flight
+  // together (one dependent step each, not four in a row)
   FT afr[2];
+  uint4 w2s[2];
+  int32_t prow[2];
+  // (unconditional loads at clamped positions, n >= 1; padding rows are
+  // replaced after the loads)
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int64_t p = wbase + g * 32 + (lane & 31);
-    const bool valid = p < n;
-    const uint4* P = job.pay + (int64_t)(valid ? job.perm[p] : 0) * PAY_WORDS;
-    if (valid) {
-      afr[g] = *(const FT*)((const uint8_t*)P + 8 * half * EB);
-    } else {
+    prow[g] = job.perm[p < n ? p : n - 1];
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const uint4* P = job.pay + (int64_t)prow[g] * PAY_WORDS;
+    afr[g] = *(const FT*)((const uint8_t*)P + 8 * half * EB);
+    w2s[g] = P[2];
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (!(wbase + g * 32 + (lane & 31) < n)) {
       __builtin_memset(&afr[g], 0, sizeof(FT));
+      w2s[g] = make_uint4(__float_as_uint(-__builtin_inff()), 0u, 0u, 0u);
     }
-    const uint4 w2 = valid ? P[2] : make_uint4(__float_as_uint(-__builtin_inff()), 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const bool valid = wbase + g * 32 + (lane & 31) < n;
+    const uint4 w2 = w2s[g];
     const float nh = __uint_as_float(w2.x);
     const float er = __uint_as_float(w2.y);
     if (half == 0) s_nh[wave][g * 32 + (lane & 31)] = nh;
