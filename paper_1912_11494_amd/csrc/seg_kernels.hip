@@ -339,8 +339,10 @@ int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const flo
                       unsigned int* flags, hipStream_t s) {
   if (m > 0) {
     const int64_t mp = (m + 7) & ~(int64_t)7;
-    prep_atlas_kernel<<<(unsigned)((mp + 255) / 256), 256, 0, s>>>(cen, m, bid, thr, nb, cprep,
-                                                                    ccen, bid_out, cext, flags);
+    // one wave per block: each lane reads a 252-byte record on its own, so the
+    // work is spread over as many CUs as there are waves
+    prep_atlas_kernel<<<(unsigned)((mp + 63) / 64), 64, 0, s>>>(cen, m, bid, thr, nb, cprep, ccen,
+                                                                bid_out, cext, flags);
   }
   if (nb > 0) check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -58,6 +58,8 @@ __global__ void pf_init_kernel(PfParams* __restrict__ prm) {
 }
 
 // One thread per centroid; wave-reduced, then one atomic per wave and axis.
+// Launched one wave per block: each lane reads its own 256-byte record, so
+// the reads are spread over as many CUs as there are waves.
 __global__ __launch_bounds__(256) void pf_bbox_kernel(const float* __restrict__ cprep, int32_t m,
                                                       PfParams* __restrict__ prm) {
   const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -511,7 +513,7 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
   uint8_t* cfeat = (uint8_t*)pb.cen_feat;
   float* cb = (float*)(cfeat + (size_t)ncols_pad * KP * EB);
   pf_init_kernel<<<1, 64, 0, s>>>(prm);
-  pf_bbox_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, prm);
+  pf_bbox_kernel<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(cprep, m, prm);
   pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)((n_pad + 63) / 64), 64, 0, s>>>(
       fibers, n, n_pad, prm, (uint8_t*)pb.fib_feat, pb.fib_h);
   pf_column_kernel<Q, MAPK, KP><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
@@ -670,7 +672,7 @@ int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* 
     pf_init_kernel<<<1, 64, 0, cs>>>(prm);
     for (int32_t a = 0; a < na; ++a)
       if (at[a].m > 0)
-        pf_bbox_kernel<<<(unsigned)((at[a].m + 255) / 256), 256, 0, cs>>>(at[a].cprep, at[a].m, prm);
+        pf_bbox_kernel<<<(unsigned)((at[a].m + 63) / 64), 64, 0, cs>>>(at[a].cprep, at[a].m, prm);
     for (int32_t i = 0; i < ns; ++i)
       if (nf[i] > 0)
         pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)(npad[i] / 64), 64, 0, cs>>>(
@@ -727,7 +729,7 @@ int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atla
 
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s) {
   pf_init_kernel<<<1, 64, 0, s>>>(prm);
-  if (m > 0) pf_bbox_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, prm);
+  if (m > 0) pf_bbox_kernel<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(cprep, m, prm);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
