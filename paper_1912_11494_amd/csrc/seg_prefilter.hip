@@ -57,25 +57,37 @@ __global__ void pf_init_kernel(PfParams* __restrict__ prm) {
   if (t < EMAX_SLOTS) prm->emax_bits[t] = 0u;
 }
 
-// One thread per centroid; wave-reduced, then one atomic per wave and axis.
-// Launched one wave per block: each lane reads its own 256-byte record, so
-// the reads are spread over as many CUs as there are waves.
-__global__ __launch_bounds__(256) void pf_bbox_kernel(const float* __restrict__ cprep, int32_t m,
-                                                      PfParams* __restrict__ prm) {
-  const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+// Bounding box of the centroid coordinates: the prepared records read as one
+// flat array of 16-byte words (coalesced, grid-stride), each float sorted to
+// its axis by its place in the 64-float record (the last float, T2, is not a
+// coordinate); reduced over the wave and the block, then one atomic per block
+// and axis.
+constexpr int BBOX_BLOCK = 256, BBOX_GRID = 64;
+__global__ __launch_bounds__(BBOX_BLOCK) void pf_bbox_kernel(const float* __restrict__ cprep,
+                                                             int32_t m,
+                                                             PfParams* __restrict__ prm) {
+  static_assert(CREC == 64 && NF == 63, "record layout");
+  __shared__ float s_red[BBOX_BLOCK / 64][6];
   float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
   float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  if (c < m) {
-    const float* p = cprep + (int64_t)c * CREC;
+  const int64_t nq = (int64_t)m * (CREC / 4);
+  for (int64_t q = (int64_t)blockIdx.x * BBOX_BLOCK + threadIdx.x; q < nq;
+       q += (int64_t)gridDim.x * BBOX_BLOCK) {
+    const float4 v4 = *(const float4*)(cprep + 4 * q);
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+    const int pos0 = (int)((4 * q) & (CREC - 1));
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float v = p[3 * i + d];
-        if (__builtin_isfinite(v)) {
-          lo[d] = fminf(lo[d], v);
-          hi[d] = fmaxf(hi[d], v);
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int pos = pos0 + i;
+      if (pos < NF && __builtin_isfinite(v[i])) {
+        const int d = pos % 3;
+        // select by axis without a dynamically indexed register array
+        lo[0] = d == 0 ? fminf(lo[0], v[i]) : lo[0];
+        hi[0] = d == 0 ? fmaxf(hi[0], v[i]) : hi[0];
+        lo[1] = d == 1 ? fminf(lo[1], v[i]) : lo[1];
+        hi[1] = d == 1 ? fmaxf(hi[1], v[i]) : hi[1];
+        lo[2] = d == 2 ? fminf(lo[2], v[i]) : lo[2];
+        hi[2] = d == 2 ? fmaxf(hi[2], v[i]) : hi[2];
       }
     }
   }
@@ -86,13 +98,32 @@ __global__ __launch_bounds__(256) void pf_bbox_kernel(const float* __restrict__ 
       hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
     }
   }
+  const int wave = threadIdx.x >> 6;
   if (lane_id() == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicMin(&prm->lo[d], ord(lo[d]));
-      atomicMax(&prm->hi[d], ord(hi[d]));
+      s_red[wave][d] = lo[d];
+      s_red[wave][3 + d] = hi[d];
     }
   }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    float r = s_red[0][k];
+    for (int w = 1; w < BBOX_BLOCK / 64; ++w) r = k < 3 ? fminf(r, s_red[w][k]) : fmaxf(r, s_red[w][k]);
+    if (k < 3)
+      atomicMin(&prm->lo[k], ord(r));
+    else
+      atomicMax(&prm->hi[k - 3], ord(r));
+  }
+}
+
+// Launch of pf_bbox_kernel (nothing for m <= 0).
+inline void launch_pf_bbox(const float* cprep, int32_t m, PfParams* prm, hipStream_t s) {
+  if (m <= 0) return;
+  const int64_t want = ((int64_t)m * (CREC / 4) + BBOX_BLOCK - 1) / BBOX_BLOCK;
+  pf_bbox_kernel<<<(unsigned)(want < BBOX_GRID ? want : BBOX_GRID), BBOX_BLOCK, 0, s>>>(cprep, m,
+                                                                                       prm);
 }
 
 // One wave per 64 fibers: the wave copies its 64 records (16 KB, contiguous)
@@ -513,7 +544,7 @@ int launch_cfg(const float* fibers, int64_t n, const float* cprep, int32_t m, co
   uint8_t* cfeat = (uint8_t*)pb.cen_feat;
   float* cb = (float*)(cfeat + (size_t)ncols_pad * KP * EB);
   pf_init_kernel<<<1, 64, 0, s>>>(prm);
-  pf_bbox_kernel<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(cprep, m, prm);
+  launch_pf_bbox(cprep, m, prm, s);
   pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)((n_pad + 63) / 64), 64, 0, s>>>(
       fibers, n, n_pad, prm, (uint8_t*)pb.fib_feat, pb.fib_h);
   pf_column_kernel<Q, MAPK, KP><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
@@ -672,7 +703,7 @@ int batch_cfg(int mode, int cfg, const BatchAtlas* at, int32_t na, const float* 
     pf_init_kernel<<<1, 64, 0, cs>>>(prm);
     for (int32_t a = 0; a < na; ++a)
       if (at[a].m > 0)
-        pf_bbox_kernel<<<(unsigned)((at[a].m + 63) / 64), 64, 0, cs>>>(at[a].cprep, at[a].m, prm);
+        launch_pf_bbox(at[a].cprep, at[a].m, prm, cs);
     for (int32_t i = 0; i < ns; ++i)
       if (nf[i] > 0)
         pf_fiber_kernel<Q, MAPK, KP><<<(unsigned)(npad[i] / 64), 64, 0, cs>>>(
@@ -729,7 +760,7 @@ int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atla
 
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s) {
   pf_init_kernel<<<1, 64, 0, s>>>(prm);
-  if (m > 0) pf_bbox_kernel<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(cprep, m, prm);
+  if (m > 0) launch_pf_bbox(cprep, m, prm, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
