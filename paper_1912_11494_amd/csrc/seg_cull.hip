@@ -512,7 +512,7 @@ __device__ __forceinline__ bool dense_pair(const float* a, const float* b, float
 // fold into the per-fiber keys (with MULTI, into the fiber's bundle slots).
 // With STATS the staged exact_pair runs instead, to count its tests.
 template <bool STATS, int QCAP, bool MULTI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void exact_list_kernel(const int2* __restrict__ list,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MULTI ? 3 : 4))) void exact_list_kernel(const int2* __restrict__ list,
                                                          const uint32_t* __restrict__ list_n,
                                                          int64_t nwaves,
                                                          const int2* __restrict__ ovf,
