@@ -1,0 +1,57 @@
+"""Host logic of bench.py that needs no GPU: the HBM-traffic table built from
+two rocprofv3 counter files (FETCH_SIZE, then WRITE_SIZE) and the 1 GiB copy
+that calibrates them."""
+import csv
+import json
+import sys
+from pathlib import Path
+
+sys.path.insert(0, str(Path(__file__).resolve().parents[1]))
+
+import bench  # noqa: E402
+
+CULL = "void seg::(anonymous namespace)::cull_kernel<1, false>(seg::CullJob, unsigned long long*)"
+CULL_STATS = "void seg::(anonymous namespace)::cull_kernel<1, true>(seg::CullJob, unsigned long long*)"
+# a non-template kernel: its name carries no return type
+RESAMPLE = ("seg::(anonymous namespace)::resample_kernel(float const*, long, long const*, long, "
+            "float*, unsigned int*)")
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _write(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for d, k, v in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": counter,
+                        "Counter_Value": v})
+
+
+def test_traffic_table(tmp_path):
+    gib_kib = float(1 << 20)
+    # the copy's fetch counter reads half its bytes (2 bytes per counted
+    # unit), its write counter all of them; a small copy is not the probe
+    fetch = [(1, COPY, gib_kib / 2), (2, COPY, 10.0), (3, CULL, 1000.0), (4, CULL, 1200.0),
+             (5, CULL_STATS, 9999.0), (6, RESAMPLE, 500.0)]
+    write = [(1, COPY, gib_kib), (2, COPY, 10.0), (3, CULL, 40.0), (4, CULL, 60.0),
+             (5, CULL_STATS, 9999.0), (6, RESAMPLE, 70.0)]
+    fp, wp, out = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "t.json"
+    _write(fp, "FETCH_SIZE", fetch)
+    _write(wp, "WRITE_SIZE", write)
+    bench.write_traffic(str(fp), str(wp), str(out))
+    d = json.loads(out.read_text())
+    cal = d["calibration"]
+    assert cal["dispatches"] == 1
+    assert abs(cal["bytes_per_kib_fetch"] - 2.0) < 1e-12
+    assert abs(cal["bytes_per_kib_write"] - 1.0) < 1e-12
+    # the timed launch (statistics off), averaged over its launches
+    c = d["cull_kernel:fp16"]
+    assert c["kernel"] == CULL
+    assert abs(c["bytes_per_launch"] - (1100.0 * 1024 * 2 + 50.0 * 1024)) < 1e-6
+    # found without a return type in its name
+    r = d["resample_kernel"]
+    assert r["kernel"] == RESAMPLE
+    assert abs(r["bytes_per_launch"] - (500.0 * 1024 * 2 + 70.0 * 1024)) < 1e-6
+    assert r["source_hash"] == bench.source_hash()
+    assert "cull_kernel:bf16" not in d
