@@ -732,6 +732,55 @@ def pin_multi_cut_equals_brute(O, seed=20):
         assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+def pin_accepted_pairs(O, seed=21):
+    """The accepted-pair list is the set {(f, c) : d_ME(f, c) <= T[bid[c]]}
+    (section 2.3: a fiber is kept for a bundle only under that bundle's own
+    threshold), in fiber-major then centroid order.  Checked against the NumPy
+    float64 brute force on pairs away from the boundary, and exactly on the
+    special thresholds: all +inf gives every one of the N*M pairs, all
+    negative gives none, and one +inf bundle among negative ones gives exactly
+    the pairs of that bundle's centroids."""
+    rng = np.random.default_rng(seed)
+    fib, cen, bid, thr = _random_set(rng, 60, 24, 6, near=0.7)
+    n, m = len(fib), len(cen)
+    d = np_fp64.dme_matrix(fib, cen)
+    t = thr.astype(np.float64)[bid]
+    acc = O.accepted_pairs_f32(fib, cen, bid, thr)
+    assert acc.ndim == 2 and acc.shape[1] == 2
+    key = acc[:, 0] * m + acc[:, 1]
+    assert (np.diff(key) > 0).all(), "pairs not in fiber-major, centroid order"
+    got = np.zeros((n, m), bool)
+    got[acc[:, 0], acc[:, 1]] = True
+    clear = np.abs(d - t[None, :]) > 1e-4 * t[None, :]
+    want = d <= t[None, :]
+    assert np.array_equal(got[clear], want[clear])
+    assert clear.mean() > 0.99 and want.sum() > 30
+    # the labels follow from the same set: a fiber is labelled iff it has a pair
+    lab, _, best = O.segment_f32(fib, cen, bid, thr, mode=BRUTE)
+    assert np.array_equal(lab >= 0, got.any(1))
+    assert all(got[f, best[f]] for f in np.nonzero(lab >= 0)[0])
+    nb = len(thr)
+    acc = O.accepted_pairs_f32(fib, cen, bid, np.full(nb, np.inf, F32))
+    ff, cc = np.meshgrid(np.arange(n), np.arange(m), indexing="ij")
+    assert np.array_equal(acc, np.stack([ff.ravel(), cc.ravel()], 1))
+    acc = O.accepted_pairs_f32(fib, cen, bid, np.full(nb, -1.0, F32))
+    assert acc.shape == (0, 2)
+    # the boundary itself: integer points 13 mm apart (exact in float32) are
+    # accepted at T = 13 and not at the next float below
+    a = np.stack([np.arange(21.0), np.zeros(21), np.zeros(21)], 1).astype(F32) + 50
+    c = (a.astype(np.float64) + [3.0, 4.0, 12.0]).astype(F32)
+    for t13, k in ((13.0, 1), (np.nextafter(F32(13.0), F32(0.0)), 0)):
+        acc = O.accepted_pairs_f32(a[None], c[None], np.zeros(1, np.int32), np.array([t13], F32))
+        assert len(acc) == k, (t13, acc)
+    for k in (0, nb - 1):
+        one = np.full(nb, -1.0, F32)
+        one[k] = np.inf
+        acc = O.accepted_pairs_f32(fib, cen, bid, one)
+        cols = np.nonzero(bid == k)[0]
+        want = np.stack([np.repeat(np.arange(n), len(cols)), np.tile(cols, n)], 1)
+        assert np.array_equal(acc, want), k
+
+
 ALL_PINS = [
     pin_expression_rounding,
     pin_straight_translation,
@@ -761,4 +810,5 @@ ALL_PINS = [
     pin_multi_single_consistency,
     pin_multi_infinite_thresholds,
     pin_multi_cut_equals_brute,
+    pin_accepted_pairs,
 ]

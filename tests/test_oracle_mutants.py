@@ -61,6 +61,10 @@ MUTANTS = {
     "multi_counts_set_not_added": ("bundle_counts[bundles[i]] += 1;", "bundle_counts[bundles[i]] = 1;"),
     "multi_threshold_of_bundle_zero": ("    float tt = t2[bid[c]];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k",
                                        "    float tt = t2[0];\n    int ok;\n    if (flags & VAR_DIR)\n      ok = mode == ORACLE_CUT ? eval_dir_cut_f32(a, b, tt, &D) : eval_dir_brute_f32(a, b, tt, &D);\n    else\n      ok = mode == ORACLE_CUT ? eval_cut_f32(a, b, tt, &D) : eval_brute_f32(a, b, tt, &D);\n    if (!ok) continue;\n    float v = D;\n    if (flags & VAR_TN) {\n      v = sqrtf(D) + oracle_tn_f32(ls, lc[c]);\n      if (!(v <= thr[bid[c]])) continue;\n    }\n    int32_t k"),
+    "accepted_threshold_of_bundle_zero": ("thr2_f32(thr[bid[c]]), &D)) {\n        if (cnt < cap)",
+                                          "thr2_f32(thr[0]), &D)) {\n        if (cnt < cap)"),
+    "accepted_skips_last_centroid": ("for (int64_t c = 0; c < m; ++c) {\n      float D;\n      if (eval_brute_f32(a, cen + (size_t)c * 3 * NP, thr2_f32(thr[bid[c]])",
+                                     "for (int64_t c = 0; c < m - 1; ++c) {\n      float D;\n      if (eval_brute_f32(a, cen + (size_t)c * 3 * NP, thr2_f32(thr[bid[c]])"),
     "resample_k_over_21": ("int64_t t = (L / 20) * k + ((L % 20) * k) / 20;",
                            "int64_t t = (L / 21) * k + ((L % 21) * k) / 21;"),
     "resample_target_rounded": ("int64_t t = (L / 20) * k + ((L % 20) * k) / 20;",
