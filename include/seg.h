@@ -57,7 +57,8 @@ typedef enum seg_status {
   SEG_ENONFINITE = -3,  /* NaN / inf coordinate or NaN threshold (validate = 1) */
   SEG_EHIP = -4,        /* a HIP runtime call failed */
   SEG_ENOMEM = -5,      /* scratch allocation failed */
-  SEG_ERANGE = -6,      /* a size beyond what the kernels index (M >= 2^24) */
+  SEG_ERANGE = -6,      /* a size beyond what the kernels index (M >= 2^24;
+                           N >= 2^31 for the tile-culled form) */
   SEG_EMODE = -7,       /* unknown mode or option value */
   SEG_EOFFSETS = -8,    /* an empty streamline or offsets outside the points (validate = 1) */
   SEG_ECAPACITY = -9    /* more label entries than the output holds (*total tells how many) */

@@ -260,6 +260,7 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
       break;
   }
   if (rc == -2) return fail(SEG_EMODE, "unknown tile configuration " + std::to_string(tile));
+  if (rc == -4) return fail(SEG_ERANGE, "the tile-culled form takes fewer than 2^31 fibers");
   if (rc) return hip_fail(hipGetLastError(), "kernel launch");
   if (o.collect_stats) {
     t_stats_counters = counters;

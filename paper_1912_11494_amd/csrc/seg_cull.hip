@@ -1091,7 +1091,7 @@ int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t 
              Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo,
              const int32_t* cperm) {
   if (n <= 0) return 0;
-  if (n >= ((int64_t)1 << 31)) return -2;  // sorted rows are indexed with 32 bits
+  if (n >= ((int64_t)1 << 31)) return -4;  // sorted rows are indexed with 32 bits
   switch (q) {
     case 0: return cull_launch<Q_BF16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo, cperm);
     case 1: return cull_launch<Q_F16>(fibers, n, cprep, m, bid, labels, dists, counters, mt, pb, ev, s, mo, cperm);

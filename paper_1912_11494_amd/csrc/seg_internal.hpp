@@ -111,6 +111,7 @@ int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
 
 // Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
+// Returns as run_prefilter, and -4 for 2^31 fibers or more.
 int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t m,
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
              Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo = nullptr,

@@ -229,7 +229,14 @@ __device__ __forceinline__ void quantise_row(const float* __restrict__ p, bool r
   *nq_out = nq;
   // the double features themselves (square roots) carry 2^-50 relative error
   *e_out = sqrt(err) * (1.0 + 0x1p-40) + 0x1p-50 * sqrt(nx) + 1e-30;
-  if (!__builtin_isfinite(err + nx + nq)) *e_out = __builtin_nan("");
+  if (!__builtin_isfinite(err + nx + nq)) {
+    // a non-finite coordinate: the curve bypasses the bound (its constant
+    // makes every product pass), so its codes must not turn the product into
+    // NaN; a bf16 code of an infinite feature would (inf * 0, inf - inf)
+    *e_out = __builtin_nan("");
+#pragma unroll
+    for (int k = 0; k < KP * T::bytes; k += 16) *(uint4*)(row + k) = make_uint4(0, 0, 0, 0);
+  }
 }
 
 // Features of fiber row f (quantised codes, the row constant -Ha and the

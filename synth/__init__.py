@@ -11,6 +11,7 @@ from .fibers import (  # noqa: F401
     WORKLOADS,
     bezier_curves,
     make_atlas,
+    gpu_in_use,
     make_fibers,
     raw_streamlines,
     raw_streamlines_torch,

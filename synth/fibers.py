@@ -38,6 +38,7 @@ Nothing here evaluates a fiber-to-centroid distance.
 """
 from __future__ import annotations
 
+import sys
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -300,14 +301,33 @@ def _chunk_job(args):
                         _rng(seed, 1, subject_idx, c))
 
 
+def gpu_in_use() -> bool:
+    """Whether this process has already initialised the GPU through torch.
+
+    A forked worker would inherit that device state, so the fiber generator
+    then draws its chunks in this process instead (same output)."""
+    torch = sys.modules.get("torch")
+    if torch is None:
+        return False
+    try:
+        return bool(torch.cuda.is_initialized())
+    except Exception:  # a torch without the cuda module: nothing initialised
+        return False
+
+
 def make_fibers(atlases: Sequence[Atlas], subject: SubjectSpec, seed: int,
                 subject_idx: int = 0, start: int = 0, count: Optional[int] = None,
                 workers: int = 1) -> np.ndarray:
     """Fibers [start, start+count) of a subject, float32 [count, 21, 3].
 
     ``workers`` > 1 draws the chunks in a pool of forked processes (same
-    output); call it before the process has touched the GPU.
+    output), unless the process has initialised the GPU (``gpu_in_use``):
+    then every chunk is drawn here, one after another.  A process whose GPU
+    was initialised by something other than torch (a profiler's preloaded
+    library) must pass ``workers=1`` itself.
     """
+    if workers > 1 and gpu_in_use():
+        workers = 1
     if count is None:
         count = subject.n_fibers - start
     if start < 0 or count < 0 or start + count > subject.n_fibers:

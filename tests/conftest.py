@@ -12,6 +12,22 @@ for p in (ROOT, HERE):
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "workloads(*names): full-size synthetic inputs the "
+                                       "test reads, drawn before any test touches the GPU")
+
+
+def pytest_collection_finish(session):
+    """Draw the full-size inputs of the selected tests now, while no test has
+    initialised the GPU (the generator forks worker processes)."""
+    names = []
+    for item in session.items:
+        m = item.get_closest_marker("workloads")
+        if m:
+            names += [n for n in m.args if n not in names]
+    if names:
+        import inputs
+
+        inputs.pregenerate(names, log=lambda msg: print(msg, flush=True))
 
 
 @pytest.fixture(scope="session")

@@ -6,6 +6,7 @@ import sys
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import synth
 
@@ -175,6 +176,7 @@ def test_autotune_roundtrip(seg, tmp_path):
     seg.tune_clear()
 
 
+@pytest.mark.workloads("batch-16-subjects-x-2-atlases")
 def test_batch_full_size_sampled(seg):
     """The batch workload at full size (16 subjects, 37M fibers, two atlases) on
     both routes; the oracle recomputes 150 fibers of every subject."""
@@ -189,7 +191,7 @@ def test_batch_full_size_sampled(seg):
     rng = np.random.default_rng(39)
     samples, gf = [], []
     for i, sp in enumerate(subs):
-        f = synth.make_fibers(atl, sp, seed, subject_idx=i, workers=8)
+        f = inputs.fibers(wl, i)
         idx = np.sort(rng.choice(len(f), 150, replace=False))
         samples.append((idx, f[idx]))
         gf.append(torch.from_numpy(f).to(d))

@@ -6,6 +6,7 @@ import sys
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import pins
 import synth
@@ -177,6 +178,7 @@ def test_multi_validation(seg):
     _same(_multi(seg, fib, cen, bid, thr, "fp16"), want, "after a rejected call")
 
 
+@pytest.mark.workloads("paper-4145k-x-10k")
 def test_multi_full_size_sampled(seg):
     """Paper-scale subject in the benchmark's configuration; the oracle
     recomputes the rows of a fixed sample of fibers."""
@@ -185,8 +187,7 @@ def test_multi_full_size_sampled(seg):
     wl = "paper-4145k-x-10k"
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]
-    log(f"multi full size: generating {subj.n_fibers} fibers")
-    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=8)
+    fib = inputs.fibers(wl)
     atlas = _atlas(seg, at.centroids, at.bundle_id, at.thresholds)
     f = torch.from_numpy(fib).to("cuda:0")
     off, bun, dst, cnt = [x.cpu().numpy() for x in atlas.segment_multi(f, mode="fp16")]

@@ -14,6 +14,7 @@ import sys
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import synth
 from gpu_common import assert_parity, run, to_gpu
@@ -133,6 +134,36 @@ def test_special_thresholds(seg, mode):
     assert (lab == -1).all() and np.isinf(dist).all()
 
 
+@pytest.mark.parametrize("mode,tile", [(m, 0) for m in ALL_MODES] +
+                         [(m, 1) for m in ("bf16", "fp16", "fp8")])
+def test_infinite_coordinates_unvalidated(seg, mode, tile):
+    """Without validation an infinite coordinate is an ordinary float32 value:
+    its point distances are +inf, so the pair is accepted by a bundle with
+    T = +inf (D = +inf <= T2) and by no other.  Fibers carry infinities in x,
+    centroids in y (no inf - inf).  Every cut must keep these pairs; a bf16
+    code of an infinite feature would make the matrix product NaN."""
+    fib, at = synth.small_case(600, 5, 9, seed=23)
+    fib = fib.copy()
+    cen = at.centroids.copy()
+    thr = at.thresholds.copy()
+    # bundle 3 (centroids 27-35) always matches, and each of its centroids has
+    # an infinite coordinate: it is the label of every fiber without a finite
+    # match, at distance +inf
+    thr[3] = np.inf
+    cen[27:36:2, 7, 1] = np.inf
+    cen[28:36:2, 10, 1] = -np.inf
+    fib[5, 3, 0] = np.inf
+    fib[77, 10, 0] = -np.inf
+    fib[400, 0, 0] = np.inf
+    fib[401, 20, 0] = np.inf
+    log(f"infinite coordinates mode={mode} tile={tile}")
+    lab, dist = run(seg, fib, cen, at.bundle_id, thr, mode, tile)
+    assert_parity(lab, dist, fib, cen, at.bundle_id, thr, ctx=f"inf {mode}:{tile}",
+                  check_f64=False)
+    assert (lab[[5, 77, 400, 401]] == 3).all() and np.isinf(dist[[5, 77, 400, 401]]).all()
+    assert (lab >= 0).all() and np.isinf(dist).sum() > 100
+
+
 @pytest.mark.parametrize("mode", ALL_MODES)
 def test_empty_and_single(seg, mode):
     import torch
@@ -235,6 +266,7 @@ def test_stats_and_determinism(seg):
         assert torch.equal(l2, lab) and torch.equal(d2, dist)
 
 
+@pytest.mark.workloads("small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k", "large-10M-x-20k")
 @pytest.mark.parametrize("wl", ["small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k",
                                 "large-10M-x-20k"])
 def test_full_size_sampled(seg, wl):
@@ -244,9 +276,7 @@ def test_full_size_sampled(seg, wl):
 
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]
-    seed = synth.workload_seed(wl)
-    log(f"full size {wl}: generating {subj.n_fibers} fibers")
-    fib = synth.make_fibers([at], subj, seed, workers=8)
+    fib = inputs.fibers(wl)
     f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
     rng = np.random.default_rng(len(wl))
     idx = np.sort(rng.choice(subj.n_fibers, 3000, replace=False))

@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import pins
 import synth
@@ -256,6 +257,7 @@ def test_segment_streamlines(seg, mode, metric):
     assert (lab >= 0).mean() > 0.3
 
 
+@pytest.mark.workloads("paper-4145k-x-10k")
 def test_resample_full_size_sampled(seg):
     """Paper-scale subject as raw streamlines (4,145,000 streamlines, about 10^9
     points at 0.2 mm steps) in the benchmark's launch configuration; the
@@ -265,8 +267,7 @@ def test_resample_full_size_sampled(seg):
     wl = "paper-4145k-x-10k"
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]
-    log(f"resample full size: generating {subj.n_fibers} fibers")
-    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=8)
+    fib = inputs.fibers(wl)
     d = torch.device("cuda:0")
     f = torch.from_numpy(fib).to(d)
     pts, off = synth.raw_streamlines_torch(f, synth.workload_seed(wl))

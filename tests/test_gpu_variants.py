@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+import inputs
 import oracle
 import synth
 from gpu_common import to_gpu
@@ -159,6 +160,7 @@ def test_unknown_metric_rejected(seg):
     assert e.value.code == -1
 
 
+@pytest.mark.workloads("paper-4145k-x-10k")
 def test_variants_full_size_sampled(seg):
     """Paper-scale subject (4.1M x 10k) in the benchmark's launch configuration
     for each variant; the oracle recomputes a fixed sample of fibers."""
@@ -167,8 +169,7 @@ def test_variants_full_size_sampled(seg):
     wl = "paper-4145k-x-10k"
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]
-    log(f"variants full size {wl}: generating {subj.n_fibers} fibers")
-    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=8)
+    fib = inputs.fibers(wl)
     f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(subj.n_fibers, 1500, replace=False))

@@ -82,3 +82,27 @@ def test_raw_streamlines_shape():
     again, off2 = synth.raw_streamlines(fib, np.random.default_rng(3), step=0.2, jitter=0.0,
                                         dup=0.5)
     assert np.array_equal(again, pts) and np.array_equal(off2, off)
+
+
+def test_no_fork_after_gpu_init(monkeypatch):
+    """Once torch has initialised the GPU, the generator draws every chunk in
+    this process (a forked worker would inherit the device state); the output
+    is the same as with the pool."""
+    import multiprocessing
+
+    import torch
+
+    at = synth.make_atlas(synth.AtlasSpec(4, 5, 20.0, 80.0, 5.0, 8.0), 3)
+    subj = synth.SubjectSpec(3 * F.CHUNK // 2, 2.0, (0.3,))
+    want = synth.make_fibers([at], subj, 8, workers=1)
+    assert not synth.gpu_in_use()
+
+    def no_pool(*a, **k):
+        raise AssertionError("a worker pool was started after GPU initialisation")
+
+    monkeypatch.setattr(torch.cuda, "is_initialized", lambda: True)
+    monkeypatch.setattr(multiprocessing.context.ForkContext, "Pool", no_pool, raising=False)
+    monkeypatch.setattr(multiprocessing.context.BaseContext, "Pool", no_pool)
+    assert synth.gpu_in_use()
+    got = synth.make_fibers([at], subj, 8, workers=4)
+    assert np.array_equal(got, want)
