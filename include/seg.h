@@ -163,6 +163,28 @@ int seg_segment(const float* fibers, int64_t n_fibers, const float* centroids,
                 const float* bundle_thresholds, int32_t n_bundles, int32_t* labels,
                 float* dists, const seg_options* opt, void* stream);
 
+/*
+ * seg_segment for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, arguments, results and errors as seg_segment in modes
+ * SEG_DENSE and SEG_PLAIN (other modes return SEG_EMODE), with every byte of
+ * library scratch (the prepared atlas, the validation flag, the statistics
+ * counters) in one fixed device array that the library's code object holds
+ * on each GPU from its first use until the process ends, about 9.4 MB.  The
+ * call makes no hipMalloc / hipFree or other allocation; it only launches
+ * kernels on `stream` (and, with opt->validate = 1, synchronises it to read
+ * the flag back, as seg_segment does).
+ *   n_centroids  at most SEG_NOALLOC_MAX_CENTROIDS, else SEG_ERANGE
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.
+ */
+#define SEG_NOALLOC_MAX_CENTROIDS 32768
+int seg_segment_noalloc(const float* fibers, int64_t n_fibers, const float* centroids,
+                        int64_t n_centroids, const int32_t* centroid_bundle_id,
+                        const float* bundle_thresholds, int32_t n_bundles, int32_t* labels,
+                        float* dists, const seg_options* opt, void* stream);
+
 /* ---- prepared atlases and batches (many subjects x one or two atlases) ---- */
 
 typedef struct seg_atlas seg_atlas;

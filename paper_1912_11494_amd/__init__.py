@@ -23,5 +23,7 @@ from .seg import (  # noqa: F401
     query_stats,
     resample,
     segment,
+    segment_noalloc,
+    NOALLOC_MAX_CENTROIDS,
     segment_batch,
 )

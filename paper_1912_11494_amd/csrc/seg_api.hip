@@ -231,9 +231,12 @@ seg_options resolve(const seg_options* opt) {
 }
 
 // Launch the per-pair path of `mode` for one subject against a prepared atlas.
-int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float* fibers, int64_t n,
-             int32_t* labels, float* dists, hipStream_t s) {
-  unsigned long long* counters = o.collect_stats ? sc->counters : nullptr;
+// `counter_buf` holds NCOUNTERS words; `pre` is the prefilter scratch (null:
+// the prefilter modes are refused).
+int run_mode(const seg_options& o, const AtlasBuf& ab, unsigned long long* counter_buf,
+             seg::PrefilterBuf* pre, const float* fibers, int64_t n, int32_t* labels,
+             float* dists, hipStream_t s) {
+  unsigned long long* counters = o.collect_stats ? counter_buf : nullptr;
   if (counters && seg::launch_fill_u64(counters, seg::NCOUNTERS, 0ull, s))
     return hip_fail(hipGetLastError(), "counter reset");
   const int32_t m = (int32_t)ab.m;
@@ -254,8 +257,9 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
       if (ev && !rc) HIP_TRY(hipEventRecord(ev[1], s));
       break;
     default:
+      if (!pre) return fail(SEG_EMODE, "this entry point runs the dense and plain modes only");
       rc = seg::run_prefilter(o.mode, tile, fibers, n, ab.cprep, ab.ccen, m, ab.bid, labels,
-                              dists, counters, mt, sc->pre, ev, s, ab.order());
+                              dists, counters, mt, *pre, ev, s, ab.order());
       if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
       break;
   }
@@ -272,6 +276,56 @@ int run_mode(const seg_options& o, const AtlasBuf& ab, Scratch* sc, const float*
     t_stats_culled = o.mode >= SEG_PREFILTER_BF16 && o.mode <= SEG_PREFILTER_FP8 &&
                      (tile == 8 || (tile == 0 && n < ((int64_t)1 << 31)));
   }
+  return 0;
+}
+
+}  // namespace
+
+// ---- scratch of the entry point that allocates nothing (seg_segment_noalloc)
+//
+// A fixed array in device memory: the validation flag, the statistics
+// counters and the prepared atlas (records, centers, bundle ids, arc length
+// and threshold) of up to SEG_NOALLOC_MAX_CENTROIDS centroids.  Every device
+// the library runs on holds its own copy from module load until the process
+// ends.  In host code the array's name is not a device address: host code
+// takes each device's address once from hipGetSymbolAddress and uses only
+// that.  Calls that overlap on one device share the array and race.
+namespace {
+constexpr int64_t kNaMaxM = SEG_NOALLOC_MAX_CENTROIDS;  // a multiple of 8
+constexpr size_t kNaFlags = 0;                          // 8 bytes
+constexpr size_t kNaCounters = 256;                     // NCOUNTERS words
+constexpr size_t kNaCprep = 512;
+constexpr size_t kNaCcen = kNaCprep + (size_t)kNaMaxM * seg::CREC_BYTES;
+constexpr size_t kNaBid = kNaCcen + (size_t)kNaMaxM * sizeof(float4);
+constexpr size_t kNaCext = kNaBid + (size_t)kNaMaxM * sizeof(int32_t);
+constexpr size_t kNaBytes = kNaCext + (size_t)kNaMaxM * 2 * sizeof(float);
+static_assert(kNaMaxM % 8 == 0, "padded atlas fits");
+static_assert(seg::NCOUNTERS * sizeof(unsigned long long) <= kNaCprep - kNaCounters, "counters fit");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaDevices = 64;
+std::mutex g_na_mu;
+unsigned char* g_na_ptr[kNaDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call there (with that device current) and kept.
+int noalloc_scratch(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaDevices) return fail(SEG_ERANGE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SEG_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_na_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_na_ptr[dev];
   return 0;
 }
 
@@ -344,7 +398,62 @@ int seg_segment(const float* fibers, int64_t n, const float* centroids, int64_t 
     rc = flags_error(f);
     if (rc) return rc;
   }
-  return run_mode(o, sc->atlas, sc, fibers, n, labels, dists, s);
+  return run_mode(o, sc->atlas, sc->counters, &sc->pre, fibers, n, labels, dists, s);
+}
+
+int seg_segment_noalloc(const float* fibers, int64_t n, const float* centroids, int64_t m,
+                        const int32_t* bid, const float* thr, int32_t nb, int32_t* labels,
+                        float* dists, const seg_options* opt, void* stream) {
+  t_err.clear();
+  const seg_options o = resolve(opt);
+  int rc = check_mode(o.mode);
+  if (!rc) rc = check_metric(o.metric);
+  if (rc) return rc;
+  if (o.mode != SEG_DENSE && o.mode != SEG_PLAIN)
+    return fail(SEG_EMODE, "seg_segment_noalloc runs the dense and plain modes");
+  if (n < 0) return fail(SEG_EINVAL, "n_fibers < 0");
+  rc = check_atlas_args(centroids, m, bid, thr, nb);
+  if (rc) return rc;
+  if (m > kNaMaxM)
+    return fail(SEG_ERANGE, "seg_segment_noalloc takes at most " + std::to_string(kNaMaxM) +
+                                " centroids");
+  if (n > 0 && (!fibers || !labels || !dists)) return fail(SEG_EINVAL, "null fiber/output pointer");
+  if (!aligned4(fibers) || !aligned4(labels) || !aligned4(dists))
+    return fail(SEG_EINVAL, "fiber/output pointers must be 4-byte aligned");
+  if (n == 0) return SEG_OK;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  unsigned long long* flags = (unsigned long long*)(base + kNaFlags);
+  unsigned long long* counters = (unsigned long long*)(base + kNaCounters);
+  // a view of the array as a prepared atlas (never released)
+  AtlasBuf ab;
+  ab.cprep = (float*)(base + kNaCprep);
+  ab.ccen = (float4*)(base + kNaCcen);
+  ab.bid = (int32_t*)(base + kNaBid);
+  ab.cext = (float*)(base + kNaCext);
+  ab.cap = kNaMaxM;
+  ab.m = m;
+  if (o.validate && seg::launch_fill_u64(flags, 1, 0ull, s))
+    return hip_fail(hipGetLastError(), "flag reset");
+  if (m > 0 && seg::launch_prep_atlas(centroids, m, bid, thr, nb, ab.cprep, ab.ccen, ab.bid,
+                                      ab.cext, (unsigned int*)flags, s))
+    return hip_fail(hipGetLastError(), "prep_atlas launch");
+  if (o.validate) {
+    if (seg::launch_check_finite(fibers, n * 63, (unsigned int*)flags, s))
+      return hip_fail(hipGetLastError(), "validation launch");
+    unsigned long long f = 0;
+    rc = read_flags(flags, s, &f);
+    if (rc) return rc;
+    rc = flags_error(f);
+    if (rc) return rc;
+  }
+  if (m == 0) {
+    if (seg::launch_fill_empty(n, labels, dists, s)) return hip_fail(hipGetLastError(), "fill");
+    return SEG_OK;
+  }
+  return run_mode(o, ab, counters, nullptr, fibers, n, labels, dists, s);
 }
 
 int seg_atlas_create(const float* centroids, int64_t m, const int32_t* bid, const float* thr,
@@ -429,7 +538,7 @@ int seg_segment_atlas(const seg_atlas* a, const float* fibers, int64_t n, int32_
     rc = flags_error(f);
     if (rc) return rc;
   }
-  return run_mode(o, a->buf, sc, fibers, n, labels, dists, s);
+  return run_mode(o, a->buf, sc->counters, &sc->pre, fibers, n, labels, dists, s);
 }
 
 int seg_segment_multi(const seg_atlas* a, const float* fibers, int64_t n, int32_t max_per_fiber,

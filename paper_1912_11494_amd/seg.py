@@ -36,6 +36,8 @@ MODES = {
     "bf16_oriented": PREFILTER_BF16_ORIENTED,
 }
 
+NOALLOC_MAX_CENTROIDS = 32768  # SEG_NOALLOC_MAX_CENTROIDS
+
 STATUS = {0: "SEG_OK", -1: "SEG_EINVAL", -2: "SEG_EBUNDLE", -3: "SEG_ENONFINITE",
           -4: "SEG_EHIP", -5: "SEG_ENOMEM", -6: "SEG_ERANGE", -7: "SEG_EMODE",
           -8: "SEG_EOFFSETS", -9: "SEG_ECAPACITY"}
@@ -84,6 +86,9 @@ def lib():
         i32 = ctypes.c_int32
         L.seg_segment.argtypes = [P, i64, P, i64, P, P, i32, P, P, ctypes.POINTER(Options), P]
         L.seg_segment.restype = ctypes.c_int
+        L.seg_segment_noalloc.argtypes = [P, i64, P, i64, P, P, i32, P, P,
+                                          ctypes.POINTER(Options), P]
+        L.seg_segment_noalloc.restype = ctypes.c_int
         L.seg_default_options.argtypes = [ctypes.POINTER(Options)]
         L.seg_last_error.restype = ctypes.c_char_p
         L.seg_version.restype = ctypes.c_int
@@ -198,6 +203,34 @@ def segment(fibers: torch.Tensor, centroids: torch.Tensor, centroid_bundle_id: t
                            centroid_bundle_id.data_ptr(), bundle_thresholds.data_ptr(),
                            bundle_thresholds.shape[0], labels.data_ptr(), dists.data_ptr(),
                            ctypes.byref(opt), _stream(stream))
+    _check(rc)
+    return labels, dists
+
+
+def segment_noalloc(fibers: torch.Tensor, centroids: torch.Tensor,
+                    centroid_bundle_id: torch.Tensor, bundle_thresholds: torch.Tensor,
+                    out: Tuple[torch.Tensor, torch.Tensor], mode="plain", validate=False, tile=0,
+                    stats=False, stream=None, events=None, metric=0) -> Tuple[torch.Tensor,
+                                                                              torch.Tensor]:
+    """seg_segment_noalloc: `segment` with caller-owned outputs and library
+    scratch in a fixed device array (dense and plain modes, at most
+    NOALLOC_MAX_CENTROIDS centroids); see include/seg.h."""
+    _dev(fibers, torch.float32, (21, 3), "fibers")
+    _dev(centroids, torch.float32, (21, 3), "centroids")
+    _dev(centroid_bundle_id, torch.int32, None, "centroid_bundle_id")
+    _dev(bundle_thresholds, torch.float32, None, "bundle_thresholds")
+    labels, dists = out
+    _dev(labels, torch.int32, None, "labels")
+    _dev(dists, torch.float32, None, "dists")
+    n = fibers.shape[0]
+    if labels.shape[0] < n or dists.shape[0] < n:
+        raise ValueError("outputs must hold one entry per fiber")
+    opt = options(mode, validate, tile, stats, events, metric)
+    rc = lib().seg_segment_noalloc(fibers.data_ptr(), n, centroids.data_ptr(),
+                                   centroids.shape[0], centroid_bundle_id.data_ptr(),
+                                   bundle_thresholds.data_ptr(), bundle_thresholds.shape[0],
+                                   labels.data_ptr(), dists.data_ptr(), ctypes.byref(opt),
+                                   _stream(stream))
     _check(rc)
     return labels, dists
 

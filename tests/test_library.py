@@ -66,3 +66,30 @@ def test_filter_and_batch_host_errors():
 def test_stats_without_call():
     st = S.Stats()
     assert P.lib().seg_query_stats(ctypes.byref(st)) == -1
+
+
+def _noalloc(n=10, m=5, nb=2, mode=S.PLAIN, fib=8, cen=16, bid=32, thr=48, lab=64, dist=80):
+    o = S.Options(mode, 0, 0, 0, None)
+    return P.lib().seg_segment_noalloc(fib, n, cen, m, bid, thr, nb, lab, dist, ctypes.byref(o),
+                                       None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(mode=S.PREFILTER_FP16), -7),          # dense and plain only
+    (dict(mode=S.PREFILTER_BF16_ORIENTED), -7),
+    (dict(mode=9), -7),
+    (dict(m=S.NOALLOC_MAX_CENTROIDS + 1), -6),  # beyond the fixed scratch
+    (dict(m=1 << 24), -6),
+    (dict(n=-1), -1),
+    (dict(fib=None), -1),
+    (dict(lab=13), -1),                         # misaligned output
+])
+def test_noalloc_host_argument_errors(kw, code):
+    """The entry point that allocates nothing rejects, on the host, modes it
+    does not run and atlases larger than its fixed scratch."""
+    assert _noalloc(**kw) == code
+    assert P.lib().seg_last_error().decode() != ""
+
+
+def test_noalloc_empty_subject_is_a_no_op():
+    assert _noalloc(n=0, fib=None, lab=None, dist=None) == 0
