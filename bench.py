@@ -49,9 +49,7 @@ TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf
                    ("seg::prefilter_kernel<2,", "prefilter_kernel:fp8"),
                    ("seg::plain_kernel<", "plain_kernel"),
                    ("seg::dense_kernel<1, false>", "dense_kernel"),
-                   ("seg::(anonymousnamespace)::cull_fiber_kernel<1>", "cull_fiber_kernel:fp16"),
-                   ("seg::(anonymousnamespace)::exact_list_kernel<false, 512, false>",
-                    "exact_list_kernel"),
+                   ("seg::(anonymousnamespace)::cull_fiber_kernel<1,", "cull_fiber_kernel:fp16"),
                    ("seg::(anonymousnamespace)::resample_kernel", "resample_kernel")]
 KERNEL_SOURCES = ["paper_1912_11494_amd/csrc/seg_device.hpp",
                   "paper_1912_11494_amd/csrc/seg_pf.hpp",
@@ -176,6 +174,67 @@ def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
     log(f"wrote {out_path}")
 
 
+# kernels whose counters are summarised: counter-file kernel-name prefix -> key
+COUNTER_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<1,false,false,false>", "cull_kernel:fp16"),
+                   ("seg::(anonymousnamespace)::cull_fiber_kernel<1,false>", "cull_fiber_kernel:fp16"),
+                   ("seg::(anonymousnamespace)::rs_scatter_kernel", "rs_scatter_kernel"),
+                   ("seg::(anonymousnamespace)::rs_hist_kernel", "rs_hist_kernel"),
+                   ("seg::plain_kernel<4,512,false>", "plain_kernel"),
+                   ("seg::dense_kernel<1,false>", "dense_kernel"),
+                   ("seg::prefilter_kernel<1,16,2,1,false,false>", "prefilter_kernel:fp16"),
+                   ("seg::(anonymousnamespace)::resample_kernel", "resample_kernel")]
+N_CU = 256
+
+
+def write_counters(csv_paths, out_path: str) -> dict:
+    """Summarise rocprofv3 --pmc counter files (one pass each) per kernel:
+    each counter averaged over the kernel's dispatches, and ratios derived
+    from them (wait and issue fractions of the wave cycles, instructions per
+    wave, matrix-core busy fraction, MFMA FLOPs)."""
+    import collections
+    import csv
+
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    names = {}
+    for path in csv_paths:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k = r["Kernel_Name"].replace(" ", "").removeprefix("void")
+                for prefix, key in COUNTER_KERNELS:
+                    if k.startswith(prefix.replace(" ", "")):
+                        acc[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                        names[key] = r["Kernel_Name"]
+    out = {}
+    for key, cs in acc.items():
+        c = {n: sum(v) / len(v) for n, v in cs.items()}
+        d = {}
+
+        def ratio(name, a, b, scale=1.0):
+            if a in c and b in c and c[b] > 0:
+                d[name] = scale * c[a] / c[b]
+
+        ratio("wait_any_frac", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES")
+        ratio("wait_inst_any_frac", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")
+        ratio("active_inst_any_frac", "SQ_ACTIVE_INST_ANY", "SQ_WAVE_CYCLES")
+        ratio("active_valu_frac", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES")
+        ratio("active_vmem_frac", "SQ_ACTIVE_INST_VMEM", "SQ_WAVE_CYCLES")
+        ratio("active_lds_frac", "SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES")
+        ratio("wave_cycles_per_wave", "SQ_WAVE_CYCLES", "SQ_WAVES")
+        for n in ("VALU", "SALU", "VMEM_RD", "VMEM_WR", "LDS", "SMEM", "MFMA"):
+            ratio(f"insts_{n.lower()}_per_wave", f"SQ_INSTS_{n}", "SQ_WAVES")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in c and c.get("GRBM_GUI_ACTIVE", 0) > 0:
+            d["mfma_busy_frac"] = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] * N_CU * 4)
+        if "SQ_INSTS_VALU_MFMA_MOPS_F16" in c:
+            d["mfma_f16_flop"] = c["SQ_INSTS_VALU_MFMA_MOPS_F16"] * 512
+        out[key] = {"kernel": names[key], "dispatches": max(len(v) for v in cs.values()),
+                    "counters": c, "derived": d, "source_hash": source_hash()}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    log(f"wrote {out_path}")
+    return out
+
+
 def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     import torch
 
@@ -210,58 +269,65 @@ def time_mode(P, hip, f, c, b, t, mode, steps, warmup, tile=0, metric=0):
     }, out
 
 
-def bench_batch(args):
-    """The batch workload: 16 subjects (0.3M-4.1M fibers) against two atlases
-    (3,600 and 10,000 centroids), one label per (fiber, atlas).  Times the
-    batch entry point (one flattened launch per atlas group in a cached HIP
-    graph) and sequential one-subject calls, and checks that they agree."""
-    import numpy as np
-    import torch
-
-    import paper_1912_11494_amd as P
+def batch_inputs(workers):
+    """Atlases and subjects of the batch workload (drawn before torch starts)."""
     import synth
 
     wl = "batch-16-subjects-x-2-atlases"
     atl = synth.workload_atlases(wl)
-    subs = synth.workload_subjects(wl)
     seed = synth.workload_seed(wl)
-    d = torch.device("cuda:0")
     t0 = time.time()
-    gf = []
-    for i, sp in enumerate(subs):
-        gf.append(torch.from_numpy(synth.make_fibers(atl, sp, seed, subject_idx=i, workers=16)).to(d))
+    subs = [synth.make_fibers(atl, sp, seed, subject_idx=i, workers=workers)
+            for i, sp in enumerate(synth.workload_subjects(wl))]
+    log(f"generated {wl}: {sum(len(f) for f in subs)} fibers in {time.time() - t0:.1f}s")
+    return atl, subs
+
+
+def bench_batch(args, atl, subs, P, hip):
+    """The batch workload: 16 subjects (0.3M-4.1M fibers) against two atlases
+    (3,600 and 10,000 centroids), one label per (fiber, atlas).  Times the
+    batch entry point on its default route (fp16, tile-culled: every subject's
+    fibers sorted together, one culled pass per atlas, in a cached HIP graph),
+    its graph-captured flattened launches (bf16 streaming, plain), and one
+    call per (subject, atlas) pair, plain and tile-culled; every route's
+    labels and distances are compared with the sequential plain calls."""
+    import torch
+
+    wl = "batch-16-subjects-x-2-atlases"
+    d = torch.device("cuda:0")
+    gf = [torch.from_numpy(f).to(d) for f in subs]
     nf = sum(int(f.shape[0]) for f in gf)
-    log(f"generated {wl}: {nf} fibers in {time.time() - t0:.1f}s")
     ga = [P.Atlas(torch.from_numpy(a.centroids).to(d), torch.from_numpy(a.bundle_id).to(d),
                   torch.from_numpy(a.thresholds).to(d)) for a in atl]
     pairs = nf * sum(a.n_centroids for a in atl)
-    hip = Hip()
     sh = torch.cuda.current_stream().cuda_stream
 
-    def timed(fn):
-        for _ in range(args.warmup):
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         e0, e1 = hip.event(), hip.event()
         hip.record(e0, sh)
-        for _ in range(args.steps):
+        for _ in range(steps):
             fn()
         hip.record(e1, sh)
         torch.cuda.synchronize()
-        return hip.elapsed(e0, e1) / args.steps
+        return hip.elapsed(e0, e1) / steps
 
     def new_outs():
         return [[(torch.empty(f.shape[0], dtype=torch.int32, device=d),
                   torch.empty(f.shape[0], dtype=torch.float32, device=d)) for _ in ga] for f in gf]
 
-    res, labels = {}, {}
-    for mode, tile in (("plain", 0), ("bf16", 1), ("fp16", 1), ("fp16", 0), ("bf16", 0)):
+    res, outs_of = {}, {}
+    steps, warmup = max(1, args.steps // 4), 1
+    for mode, tile in (("fp16", 0), ("bf16", 0), ("bf16", 1), ("plain", 0)):
         outs = new_outs()
-        ms = timed(lambda: P.segment_batch(ga, gf, mode=mode, tile=tile, outs=outs))
-        res[f"batch {mode}:{tile}"] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3)}
-        labels[f"batch {mode}:{tile}"] = outs
-        log(f"batch {mode}:{tile}: {ms:.2f} ms")
-    for mode in ("fp16", "bf16"):
+        ms = timed(lambda: P.segment_batch(ga, gf, mode=mode, tile=tile, outs=outs), steps, warmup)
+        key = f"batch {mode}:{tile}"
+        res[key] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "fibers_per_s": nf / (ms * 1e-3)}
+        outs_of[key] = outs
+        log(f"{key}: {ms:.2f} ms")
+    for mode in ("plain", "fp16"):
         outs = new_outs()
 
         def seq():
@@ -269,22 +335,81 @@ def bench_batch(args):
                 for a, at in enumerate(ga):
                     at.segment(f, mode=mode, out=outs[i][a])
 
-        ms = timed(seq)
-        res[f"sequential {mode}"] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3)}
-        labels[f"sequential {mode}"] = outs
-        log(f"sequential {mode} (tile-culled): {ms:.2f} ms")
-    ref = labels["batch plain:0"]
-    diffs = {k: int(sum(int((o[i][a][0] != ref[i][a][0]).sum()) for i in range(len(gf))
-                        for a in range(len(ga)))) for k, o in labels.items()}
-    best = min(res, key=lambda k: res[k]["ms"])
-    print(json.dumps({"metric": "fiber-centroid pairs/s, batch of 16 subjects x 2 atlases",
-                      "value": res[best]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
-                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[best]["ms"],
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                      "dtype": "f16+f32" if "fp16" in best else "f32", "data": "synthetic",
-                      "config": {"workload": f"{wl}: {nf} fibers, 3,600 + 10,000 centroids",
-                                 "fibers": nf, "best": best},
-                      "paths": res, "label_diffs_vs_batch_plain": diffs}), flush=True)
+        ms = timed(seq, steps, warmup)
+        key = f"sequential {mode}"
+        res[key] = {"ms": ms, "pairs_per_s": pairs / (ms * 1e-3), "fibers_per_s": nf / (ms * 1e-3)}
+        outs_of[key] = outs
+        log(f"{key} (one call per subject and atlas): {ms:.2f} ms")
+    ref = outs_of["sequential plain"]
+
+    def ndiff(o, k):
+        return int(sum(int((o[i][a][k] != ref[i][a][k]).sum()) for i in range(len(gf))
+                       for a in range(len(ga))))
+
+    head = "batch fp16:0"
+    for a in ga:
+        a.close()
+    return {"workload": f"{wl}: {nf:,} fibers, 3,600 + 10,000 centroids", "fibers": nf,
+            "pairs": pairs, "headline": head, "ms": res[head]["ms"],
+            "fibers_per_s": res[head]["fibers_per_s"], "pairs_per_s": res[head]["pairs_per_s"],
+            "vs_sequential_plain": res["sequential plain"]["ms"] / res[head]["ms"],
+            "vs_sequential_culled": res["sequential fp16"]["ms"] / res[head]["ms"],
+            "steps": steps, "paths": res,
+            "label_diffs_vs_sequential_plain": {k: ndiff(o, 0) for k, o in outs_of.items()},
+            "dist_diffs_vs_sequential_plain": {k: ndiff(o, 1) for k, o in outs_of.items()}}
+
+
+def bench_large(args, at, fib, P, hip):
+    """The large subject (10M fibers x 20,000 centroids): the tile-culled fp16,
+    bf16 and fp8 forms against the plain form, with survivors per fiber,
+    accepted pairs (a pair a prefilter dropped would be missing from its
+    count: false discards = plain's accepted pairs minus the mode's) and
+    label / distance differences against the plain form."""
+    import torch
+
+    d = torch.device("cuda:0")
+    f = torch.from_numpy(fib).to(d)
+    c = torch.from_numpy(at.centroids).to(d)
+    b = torch.from_numpy(at.bundle_id).to(d)
+    t = torch.from_numpy(at.thresholds).to(d)
+    N, M = fib.shape[0], at.n_centroids
+    steps, warmup = max(1, args.steps // 4), 1
+    modes, outs = {}, {}
+    for mode in ("fp16", "bf16", "fp8", "plain"):
+        r, out = time_mode(P, hip, f, c, b, t, mode, steps, warmup)
+        P.segment(f, c, b, t, mode=mode, stats=True)
+        st = P.query_stats()
+        modes[mode] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+                       "pairs_per_s": N * M / (r["ms_per_step"] * 1e-3),
+                       "fibers_per_s": N / (r["ms_per_step"] * 1e-3),
+                       "survivors_per_fiber": st["filter_pass"] / N,
+                       "accepted_pairs": st["accepted"],
+                       "bound_pairs_frac": st["bound_pairs"] / st["pairs"]}
+        outs[mode] = out
+        log(f"large {mode}: {r['ms_per_step']:.3f} ms/step, "
+            f"{modes[mode]['survivors_per_fiber']:.2f} survivors per fiber")
+    ref = outs["plain"]
+    for mode, x in modes.items():
+        x["label_diffs_vs_plain"] = int((outs[mode][0] != ref[0]).sum().item())
+        x["dist_diffs_vs_plain"] = int((outs[mode][1] != ref[1]).sum().item())
+        x["false_discards"] = modes["plain"]["accepted_pairs"] - x["accepted_pairs"]
+    foot = footprint(P, f, c, b, t, outs["fp16"])
+    del f, c, b, t, outs, ref
+    torch.cuda.empty_cache()
+    return {"workload": f"large-10M-x-20k: {WORKLOADS['large-10M-x-20k']}", "fibers": N,
+            "centroids": M, "steps": steps, "modes": modes, "headline": "fp16",
+            "device_bytes": foot}
+
+
+def footprint(P, f, c, b, t, out):
+    """Device bytes of a call: the caller's inputs and outputs, and the library
+    scratch it holds for the current stream after the call."""
+    inputs = sum(int(x.numel() * x.element_size()) for x in (f, c, b, t))
+    outputs = sum(int(x.numel() * x.element_size()) for x in out)
+    scratch = P.scratch_bytes()
+    return {"inputs": inputs, "outputs": outputs, "library_scratch": scratch,
+            "peak_total": inputs + outputs + scratch,
+            "scratch_per_fiber": scratch / max(1, int(f.shape[0]))}
 
 
 def bench_prepared(P, hip, f, c, b, t, head, args, N, ref_labels):
@@ -421,6 +546,62 @@ def bench_resample(P, hip, f, at, c, b, t, wl, head, args, N, np):
     return res
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(fib, at, ref, N, M, args, np):
+    """The CPU oracle on the host cores: the paper's progressive discard on
+    every fiber with all threads, the same on a sixteenth of the fibers with
+    one thread, and the brute-force definition on a 1% fixed-seed sample with
+    all threads (each about 10 s of CPU work or less)."""
+    import oracle
+
+    O = oracle.get()
+    thr = O.max_threads()
+    ns = N if args.cpu_sample <= 0 else min(args.cpu_sample, N)
+    h0 = time.perf_counter()
+    l_cpu, _, _ = O.segment_f32(fib[:ns], at.centroids, at.bundle_id, at.thresholds,
+                                mode=oracle.CUT, threads=thr)
+    dt = time.perf_counter() - h0
+    cpu = {"value": ns * M / dt, "unit": "pairs/s", "cores": thr, "kind": "oracle",
+           "sample": f"{'all' if ns == N else 'first'} {ns:,} of {N:,} fibers x all {M:,} "
+                     f"centroids, float32, the paper's progressive discard (tests 1-4), "
+                     f"OpenMP {thr} threads; {dt:.1f} s",
+           "fibers_per_s": ns / dt, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+           "labels_match_gpu": bool(np.array_equal(l_cpu, ref[0][:ns]))}
+    log(f"cpu oracle: {ns} fibers in {dt:.1f}s ({cpu['value']:.3e} pairs/s, {thr} threads)")
+    n1 = max(1, ns // 16)
+    h0 = time.perf_counter()
+    l1, _, _ = O.segment_f32(fib[:n1], at.centroids, at.bundle_id, at.thresholds,
+                             mode=oracle.CUT, threads=1)
+    dt1 = time.perf_counter() - h0
+    cpu["one_thread"] = {"value": n1 * M / dt1, "unit": "pairs/s", "cores": 1,
+                         "sample": f"first {n1:,} fibers, progressive discard, 1 thread; "
+                                   f"{dt1:.1f} s",
+                         "labels_match_gpu": bool(np.array_equal(l1, ref[0][:n1]))}
+    log(f"cpu oracle, 1 thread: {n1} fibers in {dt1:.1f}s")
+    rng = np.random.default_rng(11494)
+    idx = np.sort(rng.choice(N, max(1, N // 100), replace=False))
+    h0 = time.perf_counter()
+    lb, _, _ = O.segment_f32(fib[idx], at.centroids, at.bundle_id, at.thresholds,
+                             mode=oracle.BRUTE, threads=thr)
+    dtb = time.perf_counter() - h0
+    cpu["brute"] = {"value": len(idx) * M / dtb, "unit": "pairs/s", "cores": thr,
+                    "sample": f"{len(idx):,} fibers drawn with seed 11494 (1%), the definition "
+                              f"(every point of every pair), {thr} threads; {dtb:.1f} s; "
+                              f"all {N:,} fibers would take about {dtb * N / len(idx):.0f} s",
+                    "labels_match_gpu": bool(np.array_equal(lb, ref[0][idx]))}
+    log(f"cpu oracle, brute force: {len(idx)} fibers in {dtb:.1f}s")
+    return cpu
+
+
 def alg_flops(mode, st, n, m, kfeat=None):
     """Algorithmic FLOPs of the dominant kernel per launch (8 FLOP per point
     distance: 3 sub, 3 mul, 2 add; 2 per multiply-add of the matrix product).
@@ -446,7 +627,14 @@ def main():
                     help="metric variants timed on the headline mode (Eq. 3 length "
                          "normalisation `tn`, section 2.4 direction inference `dir`)")
     ap.add_argument("--batch", action="store_true",
-                    help="time the batch workload (16 subjects x 2 atlases) instead of one subject")
+                    help="time only the batch workload (16 subjects x 2 atlases)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch workload leg (16 subjects x 2 atlases)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-subject leg (10M fibers x 20,000 centroids)")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes drawing the synthetic inputs; 1 under a profiler, whose "
+                         "preloaded library has initialised the GPU before this script runs")
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the several-labels leg (every bundle a fiber passes)")
     ap.add_argument("--no-resample", action="store_true",
@@ -458,9 +646,15 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="only summarise two rocprofv3 counter files into profiles/traffic.json")
+    ap.add_argument("--counters-from", nargs="+", metavar="CSV",
+                    help="only summarise rocprofv3 --pmc counter files (one per pass) into "
+                         "profiles/counters.json")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"))
+        return
+    if args.counters_from:
+        write_counters(args.counters_from, os.path.join(ROOT, "profiles", "counters.json"))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -474,16 +668,39 @@ def main():
 
     import synth
 
+    # every input is drawn before torch starts (the generator forks workers)
+    W = max(1, args.gen_workers)
     if args.batch:
-        bench_batch(args)
+        atl, subs = batch_inputs(W)
+        import paper_1912_11494_amd as P
+
+        line = bench_batch(args, atl, subs, P, Hip())
+        print(json.dumps({"metric": "fiber-centroid pairs/s, batch of 16 subjects x 2 atlases",
+                          "value": line["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+                          "steps": line["steps"], "warmup": 1, "ms_per_step": line["ms"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f16+f32", "data": "synthetic",
+                          "config": {"workload": line["workload"], "fibers": line["fibers"]},
+                          "batch": line}), flush=True)
         return
     wl = args.workload
     at = synth.workload_atlases(wl)[0]
     subj = synth.workload_subjects(wl)[0]
     t0 = time.time()
-    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=16)
+    fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=W)
     log(f"generated {wl}: {fib.shape[0]} fibers x {at.n_centroids} centroids "
         f"in {time.time() - t0:.1f}s")
+    large_in = batch_in = None
+    if wl == "paper-4145k-x-10k" and not args.no_large:
+        wl_l = "large-10M-x-20k"
+        at_l = synth.workload_atlases(wl_l)[0]
+        t0 = time.time()
+        fib_l = synth.make_fibers([at_l], synth.workload_subjects(wl_l)[0],
+                                  synth.workload_seed(wl_l), workers=W)
+        log(f"generated {wl_l}: {fib_l.shape[0]} fibers in {time.time() - t0:.1f}s")
+        large_in = (at_l, fib_l)
+    if wl == "paper-4145k-x-10k" and not args.no_batch:
+        batch_in = batch_inputs(W)
 
     import torch
 
@@ -594,28 +811,28 @@ def main():
         log(f"variant {v} on {head}: {rv['ms_per_step']:.3f} ms/step, "
             f"{variants[v]['label_diffs_vs_exact']} labels differ from Eq. 2")
 
+    # device bytes of the headline: its call again, then the library scratch held
+    hmode, _, htile = head.partition(":")
+    hout = P.segment(f, c, b, t, mode=hmode, tile=int(htile or 0))
+    torch.cuda.synchronize()
+    foot = footprint(P, f, c, b, t, hout)
+    del hout
     prepared = bench_prepared(P, hip, f, c, b, t, head, args, N, torch.from_numpy(outs[head][0]))
     multi = None if args.no_multi else bench_multi(P, hip, f, c, b, t, head, args, N, np)
     resample = None if args.no_resample else bench_resample(P, hip, f, at, c, b, t, wl, head,
                                                             args, N, np)
 
+    large = batch = None
+    if large_in is not None:
+        large = bench_large(args, *large_in, P, hip)
+        del large_in
+    if batch_in is not None:
+        batch = bench_batch(args, *batch_in, P, hip)
+        del batch_in
+
     cpu = None
     if not args.no_cpu:
-        import oracle
-
-        ns = N if args.cpu_sample <= 0 else min(args.cpu_sample, N)
-        thr = oracle.get().max_threads()
-        h0 = time.perf_counter()
-        l_cpu, d_cpu, _ = oracle.segment_f32(fib[:ns], at.centroids, at.bundle_id, at.thresholds,
-                                            mode=oracle.CUT, threads=thr)
-        dt = time.perf_counter() - h0
-        cpu = {"value": ns * M / dt, "unit": "pairs/s", "cores": thr, "kind": "oracle",
-               "sample": f"{'all' if ns == N else 'first'} {ns:,} of {N:,} fibers x all {M:,} "
-                         f"centroids, float32, the paper's progressive discard (tests 1-4), "
-                         f"OpenMP {thr} threads; {dt:.1f} s",
-               "fibers_per_s": ns / dt,
-               "labels_match_gpu": bool(np.array_equal(l_cpu, ref[0][:ns]))}
-        log(f"cpu oracle: {ns} fibers in {dt:.1f}s ({cpu['value']:.3e} pairs/s, {thr} threads)")
+        cpu = cpu_baseline(fib, at, ref, N, M, args, np)
 
     plain_ms = modes.get("plain", {}).get("ms_per_step")
     speed = {m: plain_ms / modes[m]["ms_per_step"] for m in modes
@@ -646,6 +863,9 @@ def main():
         "prepared_atlas": prepared,
         "multi": multi,
         "resample": resample,
+        "device_bytes": foot,
+        "large": large,
+        "batch": batch,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),
     }

@@ -207,15 +207,16 @@ int seg_segment_atlas(const seg_atlas* atlas, const float* fibers, int64_t n_fib
 
 /*
  * Segment n_subjects subjects against n_atlases prepared atlases in one call.
+ * SEG_PREFILTER_BF16 / FP16 / FP8 at tile 0 (or 8) run the sorted,
+ * tile-culled form on the whole batch: the fibers of every subject get their
+ * features once (one quantisation frame over all the atlases) and are sorted
+ * together by space, then each atlas takes one culled pass over all of them.
  * SEG_PLAIN, SEG_PREFILTER_BF16_ORIENTED and the streaming tiles of the
  * symmetric prefilters run one launch of the fused kernel over a flattened
- * list of (subject, atlas, fiber block) work items, costliest atlas first;
- * the whole sequence (preparation kernels + that launch) is captured once per
- * launch shape into a HIP graph and replayed on `stream`, and all subjects
- * share one quantisation frame, so each subject's prefilter features are
- * computed once for all atlases.  SEG_PREFILTER_BF16 / FP16 / FP8 at tile 0
- * (or 8) run the sorted, tile-culled form for each (subject, atlas) pair in
- * turn on `stream` (no graph), which is faster on batches of large subjects.
+ * list of (subject, atlas, fiber block) work items, costliest atlas first.
+ * Either way the launch sequence is captured once per launch shape (the
+ * pointers and sizes of the call) into a HIP graph and replayed on `stream`;
+ * a new shape synchronises `stream` once to upload its subject table.
  * Every route gives each pair the result of the one-subject call.
  *   atlases   host array [n_atlases] of handles
  *   fibers    host array [n_subjects] of device pointers ([n][21][3] float32)
@@ -340,6 +341,12 @@ int seg_resample(const float* points, int64_t n_points, const int64_t* offsets, 
 int seg_segment_streamlines(const seg_atlas* atlas, const float* points, int64_t n_points,
                             const int64_t* offsets, int64_t n, float* fibers, int32_t* labels,
                             float* dists, const seg_options* opt, void* stream);
+
+/* Bytes of device memory the library holds as scratch for the current
+   device and `stream` (what the calls made on that stream have grown it to;
+   prepared atlases are not included): 0 when no call used the stream, -1
+   when the device cannot be queried.  Host only; no synchronisation. */
+int64_t seg_scratch_bytes(void* stream);
 
 /* Counters of the last call on this thread made with collect_stats = 1
    (synchronises that call's stream). */

@@ -21,6 +21,7 @@ from .seg import (  # noqa: F401
     header_functions,
     lib,
     query_stats,
+    scratch_bytes,
     resample,
     segment,
     segment_noalloc,

@@ -721,31 +721,34 @@ int seg_segment_batch(const seg_atlas* const* atlases, int32_t n_atlases, const 
   const bool culled = o.mode >= SEG_PREFILTER_BF16 && o.mode <= SEG_PREFILTER_FP8 &&
                       (tile == 0 || tile == 8) && nmax < ((int64_t)1 << 31);
   if (culled) {
-    // the sorted, tile-culled form, one (subject, atlas) pair after another on
-    // the stream: faster than the flattened streaming launch on batches of
-    // large subjects, and each pair's result is the one-subject call's
-    for (int32_t i = 0; i < n_subjects; ++i) {
-      if (n_fibers[i] == 0) continue;
-      for (int32_t a = 0; a < n_atlases; ++a) {
-        int32_t* lab = labels[i * n_atlases + a];
-        float* dst = dists[i * n_atlases + a];
-        if (bav[a].m == 0) {
-          if (seg::launch_fill_empty(n_fibers[i], lab, dst, s))
-            return hip_fail(hipGetLastError(), "fill");
-          continue;
-        }
-        rc = seg::run_cull(o.mode - SEG_PREFILTER_BF16, fibers[i], n_fibers[i], bav[a].cprep,
-                           bav[a].m, bav[a].bid, lab, dst, nullptr,
-                           seg::Metric{bav[a].cext, o.metric}, sc->pre, nullptr, s, nullptr,
-                           atlases[a]->buf.order());
-        if (rc == -3) return fail(SEG_ENOMEM, "prefilter scratch allocation failed");
-        if (rc) return hip_fail(hipGetLastError(), "kernel launch");
-      }
+    // the sorted, tile-culled form: every subject's fibers sorted together
+    // once, then one culled pass per atlas over all of them
+    std::vector<const int32_t*> cperms;
+    for (int32_t a = 0; a < n_atlases; ++a) {
+      if (bav[a].m > 0 && !atlases[a]->buf.order())
+        return fail(SEG_EINVAL, "a batch atlas lacks its centroid order");
+      cperms.push_back(atlases[a]->buf.order());
     }
+    rc = seg::run_cull_batch(o.mode - SEG_PREFILTER_BF16, bav.data(), n_atlases, cperms.data(),
+                             fibers, n_fibers, n_subjects, labels, dists, o.metric, sc->pre,
+                             sc->batch, s);
+    if (rc == -3) return fail(SEG_ENOMEM, "batch scratch allocation failed");
+    if (rc == -4) return fail(SEG_ERANGE, "the tile-culled batch takes fewer than 2^31 fibers");
+    if (rc) return hip_fail(hipGetLastError(), "batch launch");
     return SEG_OK;
   }
-  rc = seg::run_batch(o.mode, tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels,
-                      dists, o.metric, sc->batch, sc->pre, s);
+  // plain, the oriented map and streaming tiles: one launch of the fused kernel
+  // over a flattened list of (subject, atlas, fiber block) items, costliest
+  // atlas first, in a cached HIP graph
+  if (n_atlases == 0 || n_subjects == 0) return SEG_OK;
+  if (o.mode == SEG_PLAIN)
+    rc = seg::plain_batch(tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects, labels, dists,
+                          o.metric, sc->batch, s);
+  else if (o.mode >= SEG_PREFILTER_BF16 && o.mode <= SEG_PREFILTER_BF16_ORIENTED)
+    rc = seg::prefilter_batch(o.mode, tile, bav.data(), n_atlases, fibers, n_fibers, n_subjects,
+                              labels, dists, o.metric, sc->batch, s);
+  else
+    rc = -2;  // the dense pass has no batched form
   if (rc == -2) return fail(SEG_EMODE, "mode not supported by the batch path");
   if (rc == -3) return fail(SEG_ENOMEM, "batch scratch allocation failed");
   if (rc) return hip_fail(hipGetLastError(), "batch launch");
@@ -871,6 +874,27 @@ int seg_filter_pairs(const float* fibers, int64_t n, const float* centroids, int
   HIP_TRY(hipMemcpy(&c, sc->counters, sizeof(c), hipMemcpyDeviceToHost));
   *count = (int64_t)c;
   return SEG_OK;
+}
+
+int64_t seg_scratch_bytes(void* stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch.find(std::make_pair(dev, (hipStream_t)stream));
+  if (it == g_scratch.end()) return 0;
+  const Scratch& sc = *it->second;
+  const seg::PrefilterBuf& p = sc.pre;
+  const seg::BatchBuf& b = sc.batch;
+  int64_t t = (int64_t)sizeof(unsigned long long) * (1 + seg::NCOUNTERS);
+  t += sc.atlas.cap * (int64_t)(seg::CREC_BYTES + sizeof(float4) + 2 * sizeof(int32_t) +
+                                2 * sizeof(float));
+  t += (int64_t)(p.fib_feat_bytes + p.cen_feat_bytes + p.fib_h_bytes + p.tbox_bytes +
+                 p.keys_bytes + p.vals_bytes + p.hist_bytes + p.cperm_bytes);
+  if (p.emax) t += (int64_t)seg::pf_params_bytes();
+  t += (int64_t)(b.items_bytes + b.fib_feat_bytes + b.fib_h_bytes + b.cen_feat_bytes +
+                 b.citems_bytes);
+  t += (int64_t)(sc.mslots_bytes + sc.mscan_bytes);
+  return t;
 }
 
 int seg_query_stats(seg_stats* out) {

@@ -1,4 +1,5 @@
-// Sorted, tile-culled MFMA prefilter (symmetric feature map, K = 16).
+// Sorted, tile-culled MFMA prefilter with the exact stage fused in
+// (symmetric feature map, K = 16).
 //
 // The streaming prefilter evaluates its bound on every (fiber, centroid)
 // pair.  Most pairs are far apart, and that can be decided for whole tiles:
@@ -23,18 +24,24 @@
 // scatters with ranks from wave ballots, so equal keys keep their input
 // order and the permutation is deterministic.
 //
-// Fiber features are computed in input order (coalesced reads of the
-// records); the culled kernel reads its rows through the permutation.
+// Fiber payloads (feature codes, row constant, error bound, input index,
+// arc length) are computed in input order with coalesced reads of the
+// records; the culled kernel reads its rows through the permutation.
 //
-// Work per block (4 waves, 256 consecutive sorted rows = 8 groups of 32), in
-// rounds of 256 centroid tiles:
-//   A. each thread tests one tile against the union box of the block;
-//      passing tiles are appended to an LDS list;
-//   B. each wave tests the listed tiles against its two groups and runs the
-//      MFMA bound on the (tile, group) pairs left, loading the next tile's
-//      fragment while the current one is computed; pairs at or above the
-//      column constant go to the wave's queue and the exact stage, as in the
-//      streaming prefilter.
+// Work per wave (64 consecutive sorted rows = 2 groups of 32; the four
+// waves of a block run independently):
+//   A. each lane tests its centroid tiles against the union box of the
+//      wave's two groups, and a passing tile against each group; (tile,
+//      groups) candidates go to an LDS list, 256 tiles per round;
+//   B. for each candidate, the MFMA bound on the (tile, group) products, the
+//      next candidate's column fragment loading meanwhile; pairs at or above
+//      the column constant go to the wave's LDS survivor queue;
+//   C. the exact float32 stage on the queued pairs (when the queue fills and
+//      at the end), four lanes per pair, each lane taking the point pairs
+//      (i, 20 - i) of three values of i; accepted pairs fold into the
+//      per-row argmin keys in LDS;
+//   D. each row with an accepted centroid writes its label and distance (the
+//      fiber kernel wrote -1 / +inf to every fiber before).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -44,6 +51,7 @@
 #include <cstring>
 
 #include "seg_device.hpp"
+#include "seg_graph.hpp"
 #include "seg_internal.hpp"
 #include "seg_pf.hpp"
 
@@ -54,13 +62,8 @@ namespace {
 constexpr int CELL_AXIS_BITS = 5;
 constexpr int KPC = 16;                // feature width of the culled path
 constexpr int BOXD = KPC;              // boxed feature dimensions
-constexpr int GBOX = 2 * BOXD;         // floats per group box: lo[16], hi[16]
 constexpr int TROWS = 2 * BOXD + 1;    // tile box rows: lo[16], hi[16], radius
 constexpr float GAP_SLACK = 1.0f + 0x1p-17f;
-// survivor queue per wave (entries); handed on before a push when fewer
-// than 64 places are left
-constexpr int CULL_QCAP = 512;
-constexpr uint32_t RESCUE = 0x80000000u;  // a wave's survivor count: overflowed
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   uint32_t r = 0;
@@ -175,16 +178,12 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scan_rows_kernel(uint32_t* __re
 // block-local order: item k of digit d goes to
 //   start[d] + hist[d][b] + (k - local start of d),
 // where start[d] (the exclusive scan of the digit totals) is computed by
-// every block from the totals,
-// so each digit's run of the block is written contiguously.  With PAYLOAD,
-// the 64-byte record of each item's value moves along (the last pass of the
-// fiber sort gathers the fiber payloads into sorted order).
-template <bool PAYLOAD>
+// every block from the totals, so each digit's run of the block is written
+// contiguously.
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n,
     int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
-    int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out,
-    const uint4* __restrict__ pay_in, uint4* __restrict__ pay_out) {
+    int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
   constexpr int WAVES = RS_THREADS / 64;
   __shared__ uint32_t s_cnt[WAVES][RS_BINS];
   __shared__ uint32_t s_lstart[RS_BINS];
@@ -255,10 +254,6 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     const int32_t v = s_val[k];
     if (keys_out) keys_out[g] = key;
     vals_out[g] = v;
-    if (PAYLOAD) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) pay_out[(int64_t)g * 4 + q] = pay_in[(int64_t)v * 4 + q];
-    }
   }
 }
 
@@ -273,10 +268,11 @@ __global__ __launch_bounds__(256) void cell_key_kernel(const float* __restrict__
 
 // Per-fiber payload, 64 bytes (4 x uint4), written in input order:
 //   words 0-1  the quantised feature codes (16 codes; fp8 uses word 0)
-//   word 2     (-Ha, error bound |Xq - X|, input index, 0)
-//   word 3     zero
-// A fiber with a non-finite coordinate gets -Ha = +inf (it bypasses the cut)
-// and error bound +inf (its box is unbounded).
+//   word 2     (-Ha, error bound |Xq - X|, input index, arc length)
+//   word 3     not written, not read
+// A fiber with a non-finite coordinate gets -Ha = +inf (it bypasses the cut),
+// error bound +inf (its box is unbounded) and zero codes.  The arc length
+// (the length-normalised metric) is that of arc_length, else 0.
 constexpr int PAY_WORDS = 4;
 
 // One lane per fiber: a block takes batches of CF_BLOCK fibers (grid-stride,
@@ -285,43 +281,98 @@ constexpr int PAY_WORDS = 4;
 // 16-byte loads into registers, go to LDS, and the loads of the block's next
 // batch are issued before the lanes quantise the current one, each its own
 // record from LDS (a stride of 63 words, no bank conflict), and write its
-// payload, its center-cell key and the reset value of its argmin key.
+// payload and its cell key, and writes the empty result (-1, +inf) of the
+// fiber when `labels` is not null.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));  // 16-byte aligned
 constexpr int CF_BLOCK = 128;
 constexpr int CF_V = (CF_BLOCK * NF / 4 + CF_BLOCK - 1) / CF_BLOCK;  // loads per lane
 
-__device__ __forceinline__ void cf_load(const float* __restrict__ fibers, int64_t n, int64_t b,
-                                        int tid, f4u* v) {
-  const int64_t f0 = b * CF_BLOCK;
-  const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
-  const int n4 = (cnt * NF) >> 2;
-  const float* __restrict__ src = fibers + f0 * NF;
+// One subject of a batch as the kernels see it.
+struct SubDev {
+  const float* fibers;  // [n][21][3]
+  int64_t n;
+  int64_t row0;         // its first row among the rows of the batch
+  int64_t blk0;         // its first CF_BLOCK batch of the payload kernel
+};
+
+// Where the fibers of payload batch b come from.  One subject: fibers
+// [b * CF_BLOCK, ...) of `fibers`.  A batch of subjects (`subs`, ascending
+// blk0): the subject whose batches hold b, found by bisection.
+struct BatchSrc {
+  const float* src;  // first record
+  int cnt;           // records (at most CF_BLOCK)
+  int64_t row;       // row of the first record (payload, keys)
+  int64_t local;     // index of the first record within its subject
+  int32_t sub;       // subject
+};
+
+template <bool BATCH>
+__device__ __forceinline__ BatchSrc batch_src(int64_t b, const float* __restrict__ fibers,
+                                              int64_t n, const SubDev* __restrict__ subs,
+                                              int32_t nsub) {
+  BatchSrc r;
+  if (!BATCH) {
+    r.local = b * CF_BLOCK;
+    r.row = r.local;
+    r.sub = 0;
+    r.src = fibers + r.local * NF;
+    r.cnt = (int)(n - r.local < CF_BLOCK ? n - r.local : CF_BLOCK);
+  } else {
+    int32_t lo = 0, hi = nsub - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (subs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const SubDev sd = subs[lo];
+    r.local = (b - sd.blk0) * CF_BLOCK;
+    r.row = sd.row0 + r.local;
+    r.sub = lo;
+    r.src = sd.fibers + r.local * NF;
+    r.cnt = (int)(sd.n - r.local < CF_BLOCK ? sd.n - r.local : CF_BLOCK);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void cf_load(const BatchSrc& bs, int tid, f4u* v) {
+  const int n4 = (bs.cnt * NF) >> 2;
 #pragma unroll
   for (int u = 0; u < CF_V; ++u) {
     const int i = tid + u * CF_BLOCK;
-    if (i < n4) v[u] = *(const f4u*)(src + 4 * i);
+    if (i < n4) v[u] = *(const f4u*)(bs.src + 4 * i);
   }
 }
 
-template <int Q>
+struct FiberOut {
+  uint4* pay;          // [rows][PAY_WORDS]
+  uint32_t* keys;      // [rows] cell
+  int32_t* labels;     // one subject: [n] or null
+  float* dists;        // one subject: [n] or null
+  // a batch of subjects
+  const SubDev* subs;
+  int32_t nsub;
+  int64_t nblk;               // payload batches of all subjects
+  int32_t* const* out_lab;    // [nsub * na]: subject s against atlas a at s * na + a
+  float* const* out_dst;
+  int32_t na;
+};
+
+template <int Q, bool BATCH, bool TN>
 __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __restrict__ fibers,
                                                               int64_t n,
                                                               PfParams* __restrict__ prm,
-                                                              uint4* __restrict__ pay,
-                                                              uint32_t* __restrict__ keys,
-                                                              unsigned long long* __restrict__ fkeys) {
+                                                              FiberOut fo) {
   __shared__ float s_rec[CF_BLOCK * NF];
   const int tid = (int)threadIdx.x;
-  const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK;
+  const int64_t nb = BATCH ? fo.nblk : (n + CF_BLOCK - 1) / CF_BLOCK;
   f4u v[CF_V];
   int64_t b = blockIdx.x;
-  if (b < nb) cf_load(fibers, n, b, tid, v);
+  if (b < nb) cf_load(batch_src<BATCH>(b, fibers, n, fo.subs, fo.nsub), tid, v);
   float e32 = 0.0f;
   for (; b < nb; b += gridDim.x) {
-    const int64_t f0 = b * CF_BLOCK;
-    const int cnt = (int)(n - f0 < CF_BLOCK ? n - f0 : CF_BLOCK);
+    const BatchSrc bs = batch_src<BATCH>(b, fibers, n, fo.subs, fo.nsub);
     {
-      const int nfl = cnt * NF;
+      const int nfl = bs.cnt * NF;
       const int n4 = nfl >> 2;
 #pragma unroll
       for (int u = 0; u < CF_V; ++u) {
@@ -333,16 +384,19 @@ __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __res
           s_rec[4 * i + 3] = v[u].w;
         }
       }
-      if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = fibers[f0 * NF + 4 * n4 + tid];
+      if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = bs.src[4 * n4 + tid];
     }
     __syncthreads();
-    if (b + gridDim.x < nb) cf_load(fibers, n, b + gridDim.x, tid, v);
-    const int64_t f = f0 + tid;
-    if (tid < cnt) {
+    if (b + gridDim.x < nb)
+      cf_load(batch_src<BATCH>(b + gridDim.x, fibers, n, fo.subs, fo.nsub), tid, v);
+    const int64_t f = bs.row + tid;     // payload row
+    const int64_t loc = bs.local + tid;  // index within the subject
+    if (tid < bs.cnt) {
       float rec[NF];
 #pragma unroll
       for (int k = 0; k < NF; ++k) rec[k] = s_rec[tid * NF + k];
-      uint4* P = pay + f * PAY_WORDS;
+      fo.keys[f] = center_cell(rec, prm);
+      uint4* P = fo.pay + f * PAY_WORDS;
       if (QTraits<Q>::bytes == 1) P[1] = make_uint4(0u, 0u, 0u, 0u);
       double nq, e;
       quantise_row<Q, MAP_SYM, KPC>(rec, false, prm, (uint8_t*)P, &nq, &e);
@@ -357,10 +411,21 @@ __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __res
         er = __double2float_ru(e);
         e32 = fmaxf(e32, er);
       }
-      P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)f, 0u);
-      P[3] = make_uint4(0u, 0u, 0u, 0u);
-      keys[f] = center_cell(rec, prm);
-      fkeys[f] = NO_KEY;
+      // (a template flag, not a branch the compiler could turn into selects;
+      // from LDS: the record's registers are free by now)
+      const float len = TN ? arc_length(s_rec + tid * NF) : 0.0f;
+      P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)loc,
+                        __float_as_uint(len));
+      if (BATCH) {
+        P[3] = make_uint4((uint32_t)bs.sub, 0u, 0u, 0u);
+        for (int32_t a = 0; a < fo.na; ++a) {
+          fo.out_lab[bs.sub * fo.na + a][loc] = -1;
+          fo.out_dst[bs.sub * fo.na + a][loc] = __builtin_inff();
+        }
+      } else if (fo.labels) {
+        fo.labels[f] = -1;
+        fo.dists[f] = __builtin_inff();
+      }
     }
     __syncthreads();  // the records are read before the next batch lands
   }
@@ -370,9 +435,9 @@ __global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __res
               __float_as_uint(e32));
 }
 
-// Blocks of cull_fiber_kernel<Q> that the device holds at once (register- or
-// LDS-bound), queried once per process and quantisation.
-template <int Q>
+// Blocks of cull_fiber_kernel<Q, BATCH, TN> that the device holds at once
+// (register- or LDS-bound), queried once per process and kernel.
+template <int Q, bool BATCH, bool TN>
 int64_t cf_grid() {
   static std::atomic<int64_t> g{0};
   int64_t v = g.load(std::memory_order_relaxed);
@@ -380,14 +445,65 @@ int64_t cf_grid() {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cull_fiber_kernel<Q>, CF_BLOCK, 0) !=
-            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cull_fiber_kernel<Q, BATCH, TN>,
+                                                     CF_BLOCK, 0) != hipSuccess ||
         cus <= 0 || per <= 0)
       return 1024;
     v = (int64_t)cus * per;
     g.store(v, std::memory_order_relaxed);
   }
   return v;
+}
+
+// Order-preserving integer image of a float (its own inverse), so minima and
+// maxima can go through integer lane permutations.
+__device__ __forceinline__ int fkey(float f) {
+  const int i = __float_as_int(f);
+  return i ^ ((i >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float fkey_inv(int i) { return __int_as_float(i ^ ((i >> 31) & 0x7fffffff)); }
+
+// One DPP step of eight minima and eight maxima (lane permutation CTRL).
+template <int CTRL>
+__device__ __forceinline__ void dpp_minmax8(int* xl, int* xh) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int a = __builtin_amdgcn_mov_dpp(xl[k], CTRL, 0xF, 0xF, false);
+    const int b = __builtin_amdgcn_mov_dpp(xh[k], CTRL, 0xF, 0xF, false);
+    xl[k] = a < xl[k] ? a : xl[k];
+    xh[k] = b > xh[k] ? b : xh[k];
+  }
+}
+
+// Lowest of lo[k] and highest of hi[k] over each half wave, k < 8, as
+// wave-uniform values: lanes 0-31 give ulo[k] / uhi[k], lanes 32-63 give
+// ulo[8 + k] / uhi[8 + k].  Within each row of 16 lanes by two quad
+// permutations and rotations by 4 and 8 (all sixteen values step by step, so
+// consecutive instructions do not depend on each other), then the two rows
+// of each half through lanes 15 and 31, 47 and 63.
+__device__ __forceinline__ void half_wave_box8(const float* lo, const float* hi, float* ulo,
+                                               float* uhi) {
+  int xl[8], xh[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    xl[k] = fkey(lo[k]);
+    xh[k] = fkey(hi[k]);
+  }
+  dpp_minmax8<0xB1>(xl, xh);   // quad_perm [1,0,3,2]
+  dpp_minmax8<0x4E>(xl, xh);   // quad_perm [2,3,0,1]
+  dpp_minmax8<0x124>(xl, xh);  // row_ror:4
+  dpp_minmax8<0x128>(xl, xh);  // row_ror:8
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int l0 = __builtin_amdgcn_readlane(xl[k], 15), l1 = __builtin_amdgcn_readlane(xl[k], 31);
+    const int l2 = __builtin_amdgcn_readlane(xl[k], 47), l3 = __builtin_amdgcn_readlane(xl[k], 63);
+    const int h0 = __builtin_amdgcn_readlane(xh[k], 15), h1 = __builtin_amdgcn_readlane(xh[k], 31);
+    const int h2 = __builtin_amdgcn_readlane(xh[k], 47), h3 = __builtin_amdgcn_readlane(xh[k], 63);
+    ulo[k] = fkey_inv(l0 < l1 ? l0 : l1);
+    ulo[8 + k] = fkey_inv(l2 < l3 ? l2 : l3);
+    uhi[k] = fkey_inv(h0 > h1 ? h0 : h1);
+    uhi[8 + k] = fkey_inv(h2 > h3 ? h2 : h3);
+  }
 }
 
 // Lowest / highest over the 32 lanes of each half wave.
@@ -402,8 +518,10 @@ __device__ __forceinline__ void half_wave_box(float* lo, float* hi, int nd) {
 }
 
 // Sorted columns: column j is centroid cperm[j]; each half wave writes the
-// box and largest radius of its tile of 32 columns (struct of arrays,
-// row-major [TROWS][ntiles]).
+// box and largest radius of its tile of 32 columns, and each block (8 tiles)
+// the box and largest radius of its super-tile (struct of arrays, row-major
+// [TROWS][ntiles] and [TROWS][nsuper]).
+constexpr int SUPER = 8;  // tiles per super-tile (one column block)
 template <int Q>
 __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restrict__ cprep,
                                                           int32_t m, int32_t ncols_pad,
@@ -412,8 +530,10 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
                                                           uint8_t* __restrict__ feat,
                                                           float* __restrict__ cb,
                                                           int32_t* __restrict__ ccent,
-                                                          float* __restrict__ tbox) {
+                                                          float* __restrict__ tbox,
+                                                          float* __restrict__ sbox) {
   using T = QTraits<Q>;
+  __shared__ float s_t[SUPER][TROWS];
   const int32_t col = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   float lo[BOXD], hi[BOXD];
   float r2 = -__builtin_inff();
@@ -441,13 +561,31 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
   for (int off = 16; off > 0; off >>= 1) r2 = fmaxf(r2, __shfl_xor(r2, off));
   const int32_t tile = col >> 5;
   const int32_t ntiles = ncols_pad >> 5;
-  if ((threadIdx.x & 31) == 0 && tile < ntiles) {
+  const int h = (int)(threadIdx.x >> 5);  // tile within the block
+  if ((threadIdx.x & 31) == 0) {
 #pragma unroll
     for (int k = 0; k < BOXD; ++k) {
-      tbox[(int64_t)k * ntiles + tile] = lo[k];
-      tbox[(int64_t)(BOXD + k) * ntiles + tile] = hi[k];
+      s_t[h][k] = lo[k];
+      s_t[h][BOXD + k] = hi[k];
     }
-    tbox[(int64_t)(2 * BOXD) * ntiles + tile] = r2 * GAP_SLACK;
+    s_t[h][2 * BOXD] = r2 * GAP_SLACK;
+    if (tile < ntiles) {
+#pragma unroll
+      for (int k = 0; k < BOXD; ++k) {
+        tbox[(int64_t)k * ntiles + tile] = lo[k];
+        tbox[(int64_t)(BOXD + k) * ntiles + tile] = hi[k];
+      }
+      tbox[(int64_t)(2 * BOXD) * ntiles + tile] = r2 * GAP_SLACK;
+    }
+  }
+  __syncthreads();
+  const int32_t nsuper = (int32_t)gridDim.x;
+  if (threadIdx.x < TROWS) {
+    const int k = (int)threadIdx.x;
+    float v = s_t[0][k];
+    for (int j = 1; j < SUPER; ++j)
+      v = k < BOXD ? fminf(v, s_t[j][k]) : fmaxf(v, s_t[j][k]);
+    sbox[(int64_t)k * nsuper + blockIdx.x] = v;
   }
 }
 
@@ -459,44 +597,104 @@ struct CullJob {
   const float* cbias;    // cb per sorted column
   const int32_t* ccent;  // centroid of each sorted column
   const float* tbox;     // tile boxes [TROWS][ntiles]
+  const float* sbox;     // super-tile boxes [TROWS][nsuper]
   int32_t ntiles;
+  int32_t nsuper;
   const float* fibers;   // the subject's fiber records (input order)
   int64_t n;
   const float* cprep;    // prepared centroid records (63 coordinates + T2)
-  unsigned long long* keys;  // per-fiber argmin keys (input order)
-  int2* list;                // per wave: QCAP survivor pairs (fiber, centroid)
-  uint32_t* list_n;          // per wave: pairs in its part of `list`
-  int2* ovf;                 // survivor pairs beyond a wave's part, shared
-  unsigned long long* ovf_count;  // entries reserved in `ovf`
-  int64_t ovf_cap;
+  const int32_t* bid;    // bundle of each prepared centroid
+  int32_t* labels;       // written for fibers with an accepted centroid
+  float* dists;
+  // a batch of subjects (rows of every subject, one atlas `atlas` of `na`)
+  const SubDev* subs;
+  int32_t* const* out_lab;  // subject s against atlas a at s * na + a
+  float* const* out_dst;
+  int32_t na, atlas;
 };
 
-// Full metric of one (fiber, centroid) pair held in registers (Eq. 2): the
-// largest point distance of each order, an order dying on a point above T2
-// as in the exact stage, D the smaller maximum of the live orders.  Every
-// point is evaluated (no early exit); the accepted set and D equal those of
-// exact_pair (with the same metric flags).
-__device__ __forceinline__ bool dense_pair(const float* a, const float* b, float t2, float& D,
-                                           int flags) {
+constexpr int CW = 4;          // waves per block (each works on its own)
+constexpr int CROUND = 256;    // centroid tiles per candidate round
+constexpr int CQ = 1280;       // survivor queue entries per wave
+constexpr int CQ_ROOM = 1024;  // the most entries one (tile, group) product adds
+
+// Order the wave's LDS writes before its later LDS reads (lanes read what
+// other lanes of the same wave wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Nine consecutive floats (three points) from a 4-byte aligned address.
+__device__ __forceinline__ void load9(const float* __restrict__ p, float* v) {
+  const f4u a = *(const f4u*)p;
+  const f4u b = *(const f4u*)(p + 4);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = a.z;
+  v[3] = a.w;
+  v[4] = b.x;
+  v[5] = b.y;
+  v[6] = b.z;
+  v[7] = b.w;
+  v[8] = p[8];
+}
+
+// Eq. 2 for one (fiber a, centroid b) pair, evaluated by the four lanes of a
+// quad: sub-lane s takes the point pairs (i, 20 - i) for i = 3s, 3s+1, 3s+2
+// (s = 3: i = 9, 10 and 11, whose pairs repeat ones of 9 and 10), i.e. the
+// points 3s .. 3s+2 and 18-3s .. 20-3s of both curves, and computes for each
+// i the direct distances d(a_i, b_i), d(a_j, b_j) and the inverse ones
+// d(a_i, b_j), d(a_j, b_i) (j = 20 - i).  The largest distance and the
+// all-within-threshold flag of each order are combined over the quad; as in
+// the exact stage, an order dies on a point above T2, D is the smaller
+// maximum of the live orders, and with MF_DIR only the order chosen by the
+// end points (held by sub-lane 0) stays.  Every lane of the quad returns the
+// same result; the maxima are exact, so the result is the one-lane result.
+__device__ __forceinline__ bool quad_pair(const float* __restrict__ ar,
+                                          const float* __restrict__ br, int sl, float& D,
+                                          int flags) {
+  float A1[9], A2[9], B1[9], B2[9];
+  load9(ar + 9 * sl, A1);
+  load9(ar + 54 - 9 * sl, A2);
+  load9(br + 9 * sl, B1);
+  load9(br + 54 - 9 * sl, B2);
+  const float t2 = br[NF];
   float md = 0.0f, mi = 0.0f;
   bool ad = true, ai = true;
+  float ex0 = 0.0f, ex1 = 0.0f, ey0 = 0.0f, ey1 = 0.0f;
 #pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const int j = NP - 1 - i;
-    const float x = d2(a[3 * i], a[3 * i + 1], a[3 * i + 2], b[3 * i], b[3 * i + 1], b[3 * i + 2]);
-    const float y = d2(a[3 * i], a[3 * i + 1], a[3 * i + 2], b[3 * j], b[3 * j + 1], b[3 * j + 2]);
-    ad = ad && x <= t2;
-    ai = ai && y <= t2;
-    md = fmaxf(md, x);
-    mi = fmaxf(mi, y);
+  for (int k = 0; k < 3; ++k) {
+    const int p = 3 * k, q = 3 * (2 - k);  // point i in A1/B1, its partner 20 - i in A2/B2
+    const float x = d2(A1[p], A1[p + 1], A1[p + 2], B1[p], B1[p + 1], B1[p + 2]);
+    const float xj = d2(A2[q], A2[q + 1], A2[q + 2], B2[q], B2[q + 1], B2[q + 2]);
+    const float y = d2(A1[p], A1[p + 1], A1[p + 2], B2[q], B2[q + 1], B2[q + 2]);
+    const float yj = d2(A2[q], A2[q + 1], A2[q + 2], B1[p], B1[p + 1], B1[p + 2]);
+    ad = ad && x <= t2 && xj <= t2;
+    ai = ai && y <= t2 && yj <= t2;
+    md = fmaxf(md, fmaxf(x, xj));
+    mi = fmaxf(mi, fmaxf(y, yj));
+    if (k == 0) {
+      ex0 = x;
+      ex1 = xj;
+      ey0 = y;
+      ey1 = yj;
+    }
   }
+  int fl = (ad ? 1 : 0) | (ai ? 2 : 0);
+#pragma unroll
+  for (int off = 1; off < 4; off <<= 1) {
+    md = fmaxf(md, __shfl_xor(md, off));
+    mi = fmaxf(mi, __shfl_xor(mi, off));
+    fl &= __shfl_xor(fl, off);
+  }
+  ad = fl & 1;
+  ai = fl & 2;
   if (flags & MF_DIR) {
-    // the order with the smaller largest end-point distance (direct on ties)
-    const float x0 = d2(a[0], a[1], a[2], b[0], b[1], b[2]);
-    const float x1 = d2(a[60], a[61], a[62], b[60], b[61], b[62]);
-    const float y0 = d2(a[0], a[1], a[2], b[60], b[61], b[62]);
-    const float y1 = d2(a[60], a[61], a[62], b[0], b[1], b[2]);
-    const bool direct = fmaxf(x0, x1) <= fmaxf(y0, y1);
+    // sub-lane 0 holds the end points: i = 0 and its partner 20
+    const int dl = (int)(lane_id() & ~3u);
+    const bool direct = __shfl((int)(fmaxf(ex0, ex1) <= fmaxf(ey0, ey1)), dl) != 0;
     ad = ad && direct;
     ai = ai && !direct;
   }
@@ -504,233 +702,75 @@ __device__ __forceinline__ bool dense_pair(const float* a, const float* b, float
   return ad || ai;
 }
 
-// The exact stage on the survivors the culled kernel queued: wave w's own
-// pairs list[w * QCAP + j], j < list_n[w], then its share of the overflow
-// list.  Each lane loads its
-// fiber record (252 bytes, 4-byte aligned) and centroid record (256 bytes)
-// with 16-byte loads, all at once, then evaluates the pair; accepted pairs
-// fold into the per-fiber keys (with MULTI, into the fiber's bundle slots).
-// With STATS the staged exact_pair runs instead, to count its tests.
-template <bool STATS, int QCAP, bool MULTI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MULTI ? 3 : 4))) void exact_list_kernel(const int2* __restrict__ list,
-                                                         const uint32_t* __restrict__ list_n,
-                                                         int64_t nwaves,
-                                                         const int2* __restrict__ ovf,
-                                                         const unsigned long long* __restrict__ ovf_count,
-                                                         int64_t ovf_cap,
-                                                         const int32_t* __restrict__ perm,
-                                                         int64_t n,
-                                                         const float* __restrict__ fibers,
-                                                         const float* __restrict__ cprep,
-                                                         unsigned long long* __restrict__ keys,
-                                                         unsigned long long* __restrict__ counters,
-                                                         Metric mt, MultiOut mo) {
-  StageCounts sc{counters};
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= nwaves) return;
-  const int lane = (int)(threadIdx.x & 63);
-  // the input indices of the wave's 64 sorted rows, read up front: the rows
-  // of its own list lie in this window
-  const int64_t prow = w * 64 + lane;
-  const int32_t pwin = perm[prow < n ? prow : n - 1];
-  // 64 pairs per step, one per lane.  An entry is (sorted row, centroid);
-  // row -1 marks an unused entry, and the rows of a rescued wave are left to
-  // the rescue kernel.
-  // `own`: the wave's own list, whose rows are all the wave's own (its flag
-  // was tested already); the overflow list mixes rows of every wave
-  // `first`: the entry of this lane in the first 64, when read already
-  auto run = [&](const int2* __restrict__ src, int64_t cnt, bool own, const int2* first) {
-    for (int64_t j0 = 0; j0 < cnt; j0 += 64) {
-      const int64_t j = j0 + lane;
-      const bool pre = j0 == 0 && first;  // the same on every lane
-      int2 e = j < cnt ? (pre ? *first : src[j]) : make_int2(-1, 0);
-      bool act = e.x >= 0 && (own || !(list_n[e.x >> 6] & RESCUE));
-      int32_t fi;
-      if (pre)
-        fi = __shfl(pwin, (int)(e.x - w * 64) & 63);  // every lane takes part
-      else
-        fi = act ? perm[e.x] : 0;
-      e = act ? make_int2(fi, e.y) : make_int2(0, 0);
-      const float* ar = fibers + (int64_t)e.x * NF;
-      const float* br = cprep + (size_t)e.y * CREC;
-      float D, v;
-      bool ok;
-      if (STATS) {
-        ok = exact_pair<true>(ar, br, act, D, sc, mt.flags);
-      } else {
-        float a[NF], b[CREC];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) {
-          const f4u v = *(const f4u*)(ar + 4 * k);
-          a[4 * k] = v.x;
-          a[4 * k + 1] = v.y;
-          a[4 * k + 2] = v.z;
-          a[4 * k + 3] = v.w;
-        }
-        a[60] = ar[60];
-        a[61] = ar[61];
-        a[62] = ar[62];
-#pragma unroll
-        for (int k = 0; k < CREC / 4; ++k) {
-          const float4 v = *(const float4*)(br + 4 * k);
-          b[4 * k] = v.x;
-          b[4 * k + 1] = v.y;
-          b[4 * k + 2] = v.z;
-          b[4 * k + 3] = v.w;
-        }
-        ok = act && dense_pair(a, b, b[NF], D, mt.flags);
-      }
-      if (ok && variant_value(D, (uint32_t)e.y, (mt.flags & MF_TN) ? arc_length(ar) : 0.0f, mt, v)) {
-        if (MULTI)
-          multi_insert(mo.slots + (int64_t)e.x * mo.K, mo.K, (uint32_t)mo.bid[e.y], v, mo.flag);
-        else
-          atomicMin(&keys[e.x], (unsigned long long)make_key(v, (uint32_t)e.y));
-      }
-    }
-  };
-  // the wave's first 64 entries are read with its count, not after it (the
-  // wave's part of the list always exists; entries past the count are unused)
-  const int2 first = list[w * QCAP + lane];
-  const uint32_t cnt = list_n[w];
-  if (!(cnt & RESCUE)) run(list + w * QCAP, cnt, true, &first);  // else: the rescue kernel
-  // the shared overflow list, 64 entries per wave in turn
-  const int64_t total = (int64_t)*ovf_count < ovf_cap ? (int64_t)*ovf_count : ovf_cap;
-  for (int64_t i0 = w * 64; i0 < total; i0 += nwaves * 64)
-    run(ovf + i0, total - i0 < 64 ? total - i0 : 64, false, nullptr);
-}
-
-// Waves of the culled kernel whose survivors overflowed: each lane takes one
-// of the wave's 64 sorted rows and evaluates its fiber against every
-// centroid (the full metric, no cut), keeping the lexicographic minimum of
-// (D, centroid) over accepted centroids (with MULTI, every accepted pair goes
-// to the fiber's bundle slots).  Only for degenerate inputs (more than 512
-// survivors per 64 fibers).
-template <bool STATS, bool MULTI>
-__global__ __launch_bounds__(256) void rescue_kernel(const uint32_t* __restrict__ list_n,
-                                                     int64_t nwaves,
-                                                     const int32_t* __restrict__ perm, int64_t n,
-                                                     const float* __restrict__ fibers,
-                                                     const float* __restrict__ cprep, int32_t m,
-                                                     unsigned long long* __restrict__ keys,
-                                                     unsigned long long* __restrict__ counters,
-                                                     Metric mt, MultiOut mo) {
-  // a bounded grid walks every wave's flag; almost all are clear
-  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < nwaves;
-       w += (int64_t)gridDim.x * 4) {
-    if (!(list_n[w] & RESCUE)) continue;
-    unsigned long long naccepted = 0;
-    const int64_t row = w * 64 + (threadIdx.x & 63);
-    const bool act = row < n;
-    const int64_t f = act ? (int64_t)perm[row] : 0;
-    float a[NF];
-    const float* ar = fibers + f * NF;
-#pragma unroll
-    for (int k = 0; k < NF; ++k) a[k] = ar[k];
-    const float ls = (mt.flags & MF_TN) ? arc_length(a) : 0.0f;
-    unsigned long long best = NO_KEY;
-    for (int32_t c = 0; c < m; ++c) {
-      const float* b = cprep + (size_t)c * CREC;  // the same for every lane
-      float D, v;
-      if (act && dense_pair(a, b, b[NF], D, mt.flags)) {
-        ++naccepted;
-        if (variant_value(D, (uint32_t)c, ls, mt, v)) {
-          if (MULTI) {
-            multi_insert(mo.slots + f * mo.K, mo.K, (uint32_t)mo.bid[c], v, mo.flag);
-          } else {
-            const unsigned long long k = make_key(v, (uint32_t)c);
-            best = k < best ? k : best;
-          }
-        }
-      }
-    }
-    if (!MULTI && act) keys[f] = best;
-    if (STATS && naccepted) atomicAdd(counters + 3, naccepted);
-  }
-}
-
-// labels / distances of every fiber from its key.
-__global__ __launch_bounds__(256) void finalize_kernel(const unsigned long long* __restrict__ keys,
-                                                       int64_t n, const int32_t* __restrict__ bid,
-                                                       int32_t* __restrict__ labels,
-                                                       float* __restrict__ dists, int flags) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < n) write_result(keys[f], bid, labels + f, dists + f, flags);
-}
-
-__global__ __launch_bounds__(256) void fill_u64_n_kernel(unsigned long long* __restrict__ p,
-                                                         int64_t n, unsigned long long v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-template <int Q, bool STATS>
-__global__ __launch_bounds__(256) void cull_kernel(CullJob job,
-                                                   unsigned long long* __restrict__ counters) {
+// The tile-culled pass with the exact stage fused in; one wave per 64 sorted
+// rows (see the top of this file).  With STATS the staged exact stage of the
+// other paths runs on the queued pairs instead (one lane per pair), to count
+// its tests; with MULTI accepted pairs go to the fibers' bundle slots.
+template <int Q, bool STATS, bool MULTI, bool BATCH>
+__global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, MultiOut mo,
+                                                       unsigned long long* __restrict__ counters) {
   using FT = typename Frag<Q>::T;
   constexpr int EB = QTraits<Q>::bytes;
-  constexpr int WAVES = 4;
-  constexpr int FPW = 64;
-  constexpr int QCAP = CULL_QCAP;
-  constexpr int CH = 6;      // candidate tiles per LDS chunk
-  __shared__ int32_t s_cand[256];
-  __shared__ uint8_t s_code[WAVES][256];
-  __shared__ FT s_feat[3][CH][2][32];
-  __shared__ float s_cb[3][CH][32];
-  __shared__ uint32_t s_cent[3][CH][32];
-  __shared__ uint32_t s_ncand;
-  __shared__ float s_bbox[GBOX];
-  __shared__ float s_gbox[2 * WAVES][GBOX];
-  __shared__ uint32_t s_queue[WAVES][QCAP];
-  const int tid = (int)threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  __shared__ __attribute__((aligned(16))) float s_nh[CW][64];  // -Ha: the MFMA C operand
+  __shared__ int32_t s_idx[CW][64];                            // input index of each row
+  __shared__ float s_len[CW][64];                              // arc length (MF_TN)
+  __shared__ int32_t s_sub[CW][BATCH ? 64 : 1];                // subject (a batch)
+  __shared__ uint32_t s_sup[CW][64];                           // passing super-tiles
+  __shared__ uint32_t s_cand[CW][CROUND];                      // passing tiles
+  __shared__ uint32_t s_q[CW][CQ];                             // centroid << 6 | row
+  __shared__ unsigned long long s_best[CW][64];                // argmin key of each row
+  const int lane = (int)(threadIdx.x & 63);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int half = lane >> 5;
-  const int64_t bbase = (int64_t)blockIdx.x * 256;
-  const int64_t wbase = bbase + wave * FPW;
+  const int l31 = lane & 31;
   const int64_t n = job.n;
+  const int64_t wbase = ((int64_t)blockIdx.x * CW + wave) * 64;
+  if (wbase >= n) return;  // the whole wave: no block-level synchronisation follows
   const int32_t ntiles = job.ntiles;
-  uint32_t* wq = s_queue[wave];
+  const bool g1 = wbase + 32 < n;  // group 1 holds a row
+  StageCounts sc{counters};
 
-  // the wave's two groups of 32 sorted positions: rows through the
-  // permutation (a position past n is a padding row: zero codes, never
-  // passes, empty box)
-  // -Ha of the wave's 64 rows: the MFMA C operand, read when a product runs
-  __shared__ __attribute__((aligned(16))) float s_nh[WAVES][FPW];
-  const double is = frame(job.prm, Q).is;
   // both groups' permutation entries, then both groups' payloads, in flight
-  // together (one dependent step each, not four in a row)
+  // together; positions past n are padding rows (zero codes, never pass,
+  // empty box)
   FT afr[2];
   uint4 w2s[2];
   int32_t prow[2];
-  // (unconditional loads at clamped positions, n >= 1; padding rows are
-  // replaced after the loads)
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    const int64_t p = wbase + g * 32 + (lane & 31);
-    prow[g] = job.perm[p < n ? p : n - 1];
+    const int64_t p = wbase + g * 32 + l31;
+    const int32_t r = job.perm[p < n ? p : n - 1];
+    prow[g] = r >= 0 && r < n ? r : 0;  // (always in range; the clamp only guards the reads)
   }
+  uint32_t sub[2] = {0u, 0u};
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const uint4* P = job.pay + (int64_t)prow[g] * PAY_WORDS;
     afr[g] = *(const FT*)((const uint8_t*)P + 8 * half * EB);
     w2s[g] = P[2];
+    if (BATCH) sub[g] = P[3].x;
+  }
+  const float isf = (float)frame(job.prm, Q).is;  // a power of two
+  // the union box of the wave's rows: each lane's 8 features of its two
+  // rows, widened by the rows' error bounds, reduced over the half wave
+  float lo[8], hi[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    lo[k] = __builtin_inff();
+    hi[k] = -__builtin_inff();
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    if (!(wbase + g * 32 + (lane & 31) < n)) {
-      __builtin_memset(&afr[g], 0, sizeof(FT));
-      w2s[g] = make_uint4(__float_as_uint(-__builtin_inff()), 0u, 0u, 0u);
+    const bool valid = wbase + g * 32 + l31 < n;
+    if (!valid) __builtin_memset(&afr[g], 0, sizeof(FT));
+    const float er = __uint_as_float(w2s[g].y);
+    if (half == 0) {
+      // a padding row's C operand is NaN: its products are NaN and never pass
+      s_nh[wave][g * 32 + l31] = valid ? __uint_as_float(w2s[g].x) : __builtin_nanf("");
+      s_idx[wave][g * 32 + l31] = valid ? (int32_t)w2s[g].z : 0;
+      s_len[wave][g * 32 + l31] = __uint_as_float(w2s[g].w);
+      if (BATCH) s_sub[wave][g * 32 + l31] = valid ? (int32_t)sub[g] : 0;
     }
-  }
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const bool valid = wbase + g * 32 + (lane & 31) < n;
-    const uint4 w2 = w2s[g];
-    const float nh = __uint_as_float(w2.x);
-    const float er = __uint_as_float(w2.y);
-    if (half == 0) s_nh[wave][g * 32 + (lane & 31)] = nh;
-    // this lane's 8 features of the row, widened by the row's error bound
-    float lo[8], hi[8];
     uint8_t codes[sizeof(FT)];
     __builtin_memcpy(codes, &afr[g], sizeof(FT));
 #pragma unroll
@@ -740,38 +780,27 @@ __global__ __launch_bounds__(256) void cull_kernel(CullJob job,
         b = (uint32_t)codes[2 * k] | ((uint32_t)codes[2 * k + 1] << 8);
       else
         b = codes[k];
-      const float xq = (float)(QTraits<Q>::dec(b) * is);  // exact
+      const float xq = QTraits<Q>::decf(b) * isf;  // exact (a power-of-two scale)
       const float l = xq - er, h = xq + er;
       // one rounding each: widen by a relative 2^-23 (and a tiny absolute)
-      lo[k] = l - fabsf(l) * 0x1p-23f - 0x1p-126f;
-      hi[k] = h + fabsf(h) * 0x1p-23f + 0x1p-126f;
-      if (!valid) {
-        lo[k] = __builtin_inff();
-        hi[k] = -__builtin_inff();
-      } else if (!(er < __builtin_inff())) {
-        lo[k] = -__builtin_inff();
-        hi[k] = __builtin_inff();
+      float rl = l - fabsf(l) * 0x1p-23f - 0x1p-126f;
+      float rh = h + fabsf(h) * 0x1p-23f + 0x1p-126f;
+      if (!(er < __builtin_inff())) {  // a non-finite row: unbounded
+        rl = -__builtin_inff();
+        rh = __builtin_inff();
       }
-    }
-    half_wave_box(lo, hi, 8);
-    if ((lane & 31) == 0) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        s_gbox[2 * wave + g][8 * half + k] = lo[k];
-        s_gbox[2 * wave + g][BOXD + 8 * half + k] = hi[k];
+      if (valid) {
+        lo[k] = fminf(lo[k], rl);
+        hi[k] = fmaxf(hi[k], rh);
       }
     }
   }
-  if (tid == 0) s_ncand = 0;
-  __syncthreads();
-  // union of the block's 8 group boxes
-  if (tid < GBOX) {
-    float v = s_gbox[0][tid];
-    for (int j = 1; j < 2 * WAVES; ++j)
-      v = tid < BOXD ? fminf(v, s_gbox[j][tid]) : fmaxf(v, s_gbox[j][tid]);
-    s_bbox[tid] = v;
-  }
-  __syncthreads();
+  // wave-uniform (scalar) union box: features 0-7 from half 0, 8-15 from
+  // half 1
+  float ulo[BOXD], uhi[BOXD];
+  half_wave_box8(lo, hi, ulo, uhi);
+  s_best[wave][lane] = NO_KEY;
+  wave_lds_sync();
 
   auto negh = [&](int g) {
     f32x16 c;
@@ -785,167 +814,178 @@ __global__ __launch_bounds__(256) void cull_kernel(CullJob job,
     }
     return c;
   };
-  uint32_t qn = 0;
-  // The first time the queue is handed on, it goes to the wave's part of the
-  // survivor list; later hand-overs reserve room in the shared overflow list
-  // (one atomic each).  The exact-stage kernel runs both.  Without room, the
-  // reserved slots that exist are marked unused and the wave is marked for
-  // the rescue kernel (top bit of its count), which evaluates its fibers
-  // against every centroid; the exact-stage kernel then skips the wave's
-  // own part.
-  const int64_t wid = wbase / FPW;
-  bool listed = false;
-  auto flush = [&]() {
-    if (STATS && lane == 0 && qn) atomicAdd(counters + 0, (unsigned long long)qn);
-    if (!listed) {
-      for (uint32_t j = lane; j < qn; j += 64) {
-        const uint32_t e = wq[j];
-        job.list[wid * QCAP + j] = make_int2((int32_t)(wbase + (e & 0xffu)), (int32_t)(e >> 8));
-      }
-      if (lane == 0) job.list_n[wid] = qn;
-      listed = true;
-    } else if (qn) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(job.ovf_count, (unsigned long long)qn);
-      base = __shfl(base, 0);
-      const bool room = (int64_t)(base + qn) <= job.ovf_cap;
-      for (uint32_t j = lane; j < qn; j += 64) {
-        if ((int64_t)(base + j) >= job.ovf_cap) break;
-        const uint32_t e = wq[j];
-        job.ovf[base + j] =
-            room ? make_int2((int32_t)(wbase + (e & 0xffu)), (int32_t)(e >> 8)) : make_int2(-1, 0);
-      }
-      if (!room && lane == 0) job.list_n[wid] = RESCUE;
-    }
-    qn = 0;
+  // the fiber record of row `slot` (input index f)
+  auto frec = [&](int slot, int32_t f) {
+    const float* base = BATCH ? job.subs[s_sub[wave][slot]].fibers : job.fibers;
+    return base + (int64_t)f * NF;
   };
-  // survivors of one (tile, group) product: every (fiber, column) at or
-  // above the column constant is queued
+  // an accepted pair: into the row's argmin key, or the fiber's bundle slots
+  auto fold = [&](int slot, int32_t f, uint32_t c, float v) {
+    if (MULTI)
+      multi_insert(mo.slots + (int64_t)f * mo.K, mo.K, (uint32_t)mo.bid[c], v, mo.flag);
+    else
+      atomicMin(&s_best[wave][slot], (unsigned long long)make_key(v, c));
+  };
+  // C: the exact stage on queue entries [0, cnt)
+  auto drain = [&](uint32_t cnt) {
+    wave_lds_sync();
+    if (STATS && lane == 0) {
+      atomicAdd(counters + 0, (unsigned long long)cnt);
+      atomicAdd(counters + 4, 1ull);
+    }
+    if constexpr (STATS) {
+      for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const bool act = j < cnt;
+        const uint32_t e = act ? s_q[wave][j] : 0u;
+        const int slot = (int)(e & 63u);
+        const uint32_t c = e >> 6;
+        const int32_t f = s_idx[wave][slot];
+        const float* ar = frec(slot, f);
+        float D, v;
+        const bool ok = exact_pair<true>(ar, job.cprep + (size_t)c * CREC, act, D, sc, mt.flags);
+        if (ok && variant_value(D, c, s_len[wave][slot], mt, v)) fold(slot, f, c, v);
+      }
+    } else {
+      const int sl = lane & 3;
+      for (uint32_t j0 = 0; j0 < cnt; j0 += 16) {
+        const uint32_t j = j0 + (uint32_t)(lane >> 2);
+        const bool act = j < cnt;
+        const uint32_t e = act ? s_q[wave][j] : 0u;  // inactive quads read row 0, centroid 0
+        const int slot = (int)(e & 63u);
+        const uint32_t c = e >> 6;
+        const int32_t f = s_idx[wave][slot];
+        float D, v;
+        const bool ok = quad_pair(frec(slot, f), job.cprep + (size_t)c * CREC, sl, D, mt.flags);
+        if (sl == 0 && act && ok && variant_value(D, c, s_len[wave][slot], mt, v))
+          fold(slot, f, c, v);
+      }
+    }
+    wave_lds_sync();
+  };
+  uint32_t qn = 0;
+  // survivors of one (tile, group) product: every (row, column) at or above
+  // the column constant is queued (the caller made room for 1024); padding
+  // rows are NaN and never pass
+  // (row r of the lane's outputs is row 8 (r / 4) + 4 half + r % 4 of the
+  // group: the entry of output r is ebase + 8 (r / 4) + r % 4)
   auto extract = [&](const f32x16& a, int g, uint32_t cent, float cbv) {
+    const uint32_t ebase = (cent << 6) | (uint32_t)(g * 32 + 4 * half);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int slot = g * 32 + out_row(lane, r);
-      const bool p = a[r] >= cbv && wbase + slot < n;
+      const uint32_t e = ebase + (uint32_t)(8 * (r >> 2) + (r & 3));
+      const bool p = a[r] >= cbv;
       const uint64_t msk = __ballot(p);
       if (!msk) continue;
-      if (qn > (uint32_t)(QCAP - 64)) flush();
-      if ((msk >> lane) & 1ull) wq[qn + bits_below(msk)] = (cent << 8) | (uint32_t)slot;
+      if (p) s_q[wave][qn + bits_below(msk)] = e;
       qn += (uint32_t)__popcll(msk);
     }
   };
-  // candidate tiles pass through three LDS chunk buffers of CH tiles: thread
-  // tid < 32 * CH owns column tid % 32 of tile tid / 32 of a chunk
-  static_assert(32 * CH <= 256, "one chunk column per thread");
-  FT gfe[2];
-  float gcb = 0.0f;
-  uint32_t gcent = 0;
-  auto gload = [&](int32_t chunk, int32_t nc) {
-    const int32_t i = chunk * CH + (tid >> 5);
-    if (tid < 32 * CH && i < nc) {
-      const int32_t col = s_cand[i] * 32 + (tid & 31);
-      const uint8_t* src = job.cfeat + (int64_t)col * (KPC * EB);
-      gfe[0] = *(const FT*)(src);
-      gfe[1] = *(const FT*)(src + 8 * EB);
-      gcb = job.cbias[col];
-      gcent = (uint32_t)job.ccent[col];
-    }
-  };
-  auto lstore = [&](int b, int32_t chunk, int32_t nc) {
-    const int32_t i = chunk * CH + (tid >> 5);
-    if (tid < 32 * CH && i < nc) {
-      const int tl = tid >> 5, j = tid & 31;
-      s_feat[b][tl][0][j] = gfe[0];
-      s_feat[b][tl][1][j] = gfe[1];
-      s_cb[b][tl][j] = gcb;
-      s_cent[b][tl][j] = gcent;
-    }
+  auto cload = [&](uint32_t i, FT& b, float& cb, uint32_t& cn) {
+    const int64_t col = (int64_t)s_cand[wave][i] * 32 + l31;
+    b = *(const FT*)(job.cfeat + col * (KPC * EB) + 8 * half * EB);
+    cb = job.cbias[col];
+    cn = (uint32_t)job.ccent[col];
   };
 
-  const float* gb0 = s_gbox[2 * wave];
-  const float* gb1 = s_gbox[2 * wave + 1];
-  for (int32_t t0 = 0; t0 < ntiles; t0 += 256) {
-    // A: tiles against the block's box
-    {
-      const int32_t t = t0 + tid;
-      bool pass = false;
-      if (t < ntiles) {
-        float s0 = 0.0f;
-#pragma unroll 4
-        for (int k = 0; k < BOXD; ++k) {
-          const float tl = job.tbox[(int64_t)k * ntiles + t];
-          const float th = job.tbox[(int64_t)(BOXD + k) * ntiles + t];
-          const float g = fmaxf(fmaxf(tl - s_bbox[BOXD + k], s_bbox[k] - th), 0.0f);
-          s0 = __builtin_fmaf(g, g, s0);
-        }
-        pass = !(s0 > job.tbox[(int64_t)(2 * BOXD) * ntiles + t]);
-      }
-      const uint64_t msk = __ballot(pass);
-      uint32_t base = 0;
-      if (lane == 0 && msk) base = atomicAdd(&s_ncand, (uint32_t)__popcll(msk));
-      base = __shfl(base, 0);
-      if (pass) s_cand[base + bits_below(msk)] = t;
+  // gap^2 of box row `i` of a [TROWS][cnt] struct-of-arrays table against
+  // the union box; passes when it does not exceed the stored radius
+  // whether box row `i` of a [TROWS][cnt] struct-of-arrays table is near the
+  // union box: gap^2 not above the stored radius
+  // (32-bit offsets from a wave-uniform row address: the table has at most
+  // TROWS * 2^19 entries)
+  auto near = [&](const float* __restrict__ box, uint32_t cnt, uint32_t i) {
+    float tl[BOXD], th[BOXD];
+#pragma unroll
+    for (int k = 0; k < BOXD; ++k) {
+      tl[k] = (box + (size_t)k * cnt)[i];
+      th[k] = (box + (size_t)(BOXD + k) * cnt)[i];
     }
-    __syncthreads();
-    const int32_t nc = (int32_t)s_ncand;
-    // B: the listed tiles against the wave's two groups (a code per
-    // candidate: bit 0 group 0 runs, bit 1 group 1 runs)
-    for (int32_t i = lane; i < nc; i += 64) {
-      const int32_t t = s_cand[i];
-      float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll 4
-      for (int k = 0; k < BOXD; ++k) {
-        const float tl = job.tbox[(int64_t)k * ntiles + t];
-        const float th = job.tbox[(int64_t)(BOXD + k) * ntiles + t];
-        const float g0 = fmaxf(fmaxf(tl - gb0[BOXD + k], gb0[k] - th), 0.0f);
-        const float g1 = fmaxf(fmaxf(tl - gb1[BOXD + k], gb1[k] - th), 0.0f);
-        s0 = __builtin_fmaf(g0, g0, s0);
-        s1 = __builtin_fmaf(g1, g1, s1);
+    const float r2 = (box + (size_t)(2 * BOXD) * cnt)[i];
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < BOXD; ++k) {
+      const float g = fmaxf(fmaxf(tl[k] - uhi[k], ulo[k] - th[k]), 0.0f);
+      s = __builtin_fmaf(g, g, s);
+    }
+    return !(s > r2);
+  };
+  // B: the MFMA bound on candidate tiles [0, nc), the next one's columns
+  // loading meanwhile; both groups (group 1 only when it holds a row)
+  auto products = [&](uint32_t nc) {
+    wave_lds_sync();
+    if (STATS && lane == 0)
+      atomicAdd(counters + 5, (unsigned long long)nc * (g1 ? 2u : 1u));
+    FT bn;
+    float cbn = 0.0f;
+    uint32_t cnn = 0;
+    cload(0, bn, cbn, cnn);
+    for (uint32_t i = 0; i < nc; ++i) {
+      const FT b = bn;
+      const float cbv = cbn;
+      const uint32_t cent = cnn;
+      if (i + 1 < nc) cload(i + 1, bn, cbn, cnn);
+      if (qn > (uint32_t)(CQ - CQ_ROOM)) {
+        drain(qn);
+        qn = 0;
       }
-      const float r2 = job.tbox[(int64_t)(2 * BOXD) * ntiles + t];
-      const bool p0 = !(s0 > r2) && wbase < n;  // a group of padding rows never runs
-      const bool p1 = !(s1 > r2) && wbase + 32 < n;
-      s_code[wave][i] = (uint8_t)(p0 | (p1 << 1));
-      if (STATS) {
-        const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
-        if (lane == 0 && (m0 | m1))
-          atomicAdd(counters + 5, (unsigned long long)(__popcll(m0) + __popcll(m1)));
+      {
+        const f32x16 a = Frag<Q>::mfma(afr[0], b, negh(0));
+        if (wave_any(max16(a) >= cbv)) extract(a, 0, cent, cbv);
+      }
+      if (g1) {
+        if (qn > (uint32_t)(CQ - CQ_ROOM)) {
+          drain(qn);
+          qn = 0;
+        }
+        const f32x16 a = Frag<Q>::mfma(afr[1], b, negh(1));
+        if (wave_any(max16(a) >= cbv)) extract(a, 1, cent, cbv);
       }
     }
-    // C: the MFMA bound on the (tile, group) pairs left, chunk by chunk
-    const int32_t nchunks = (nc + CH - 1) / CH;
-    gload(0, nc);
-    lstore(0, 0, nc);
-    gload(1, nc);
-    lstore(1, 1, nc);
-    __syncthreads();
-    int buf = 0;
-    for (int32_t k = 0; k < nchunks; ++k) {
-      gload(k + 2, nc);
-      const int32_t ulim = nc - k * CH < CH ? nc - k * CH : CH;
-      for (int u = 0; u < ulim; ++u) {
-        const uint32_t code = __builtin_amdgcn_readfirstlane(s_code[wave][k * CH + u]);
-        if (!code) continue;
-        const FT b = s_feat[buf][u][half][lane & 31];
-        const float cbv = s_cb[buf][u][lane & 31];
-        if (code & 1u) {
-          const f32x16 a = Frag<Q>::mfma(afr[0], b, negh(0));
-          if (wave_any(max16(a) >= cbv)) extract(a, 0, s_cent[buf][u][lane & 31], cbv);
-        }
-        if (code & 2u) {
-          const f32x16 a = Frag<Q>::mfma(afr[1], b, negh(1));
-          if (wave_any(max16(a) >= cbv)) extract(a, 1, s_cent[buf][u][lane & 31], cbv);
-        }
+    wave_lds_sync();  // the candidate list is rewritten after this
+  };
+
+  // A: super-tiles (8 tiles) against the union box, 64 at a time; the tiles
+  // of the passing ones, 8 super-tiles at a time
+  const int32_t nsuper = job.nsuper;
+  uint32_t nc = 0;
+  for (int32_t s0 = 0; s0 < nsuper; s0 += 64) {
+    const int32_t st = s0 + lane;
+    const bool ps = st < nsuper && near(job.sbox, (uint32_t)nsuper, (uint32_t)st);
+    const uint64_t msk = __ballot(ps);
+    if (!msk) continue;
+    if (ps) s_sup[wave][bits_below(msk)] = (uint32_t)st;
+    const uint32_t nsup = (uint32_t)__popcll(msk);
+    wave_lds_sync();
+    for (uint32_t i0 = 0; i0 < nsup; i0 += 64 / SUPER) {
+      const uint32_t i = i0 + (uint32_t)(lane / SUPER);
+      const int32_t t = i < nsup ? (int32_t)s_sup[wave][i] * SUPER + (lane % SUPER) : ntiles;
+      const bool pt = t < ntiles && near(job.tbox, (uint32_t)ntiles, (uint32_t)t);
+      const uint64_t m2 = __ballot(pt);
+      if (pt) s_cand[wave][nc + bits_below(m2)] = (uint32_t)t;
+      nc += (uint32_t)__popcll(m2);
+      if (nc > (uint32_t)(CROUND - 64)) {
+        products(nc);
+        nc = 0;
       }
-      // chunk k+2 goes into the buffer of chunk k-1 (nobody reads it any more)
-      lstore(buf == 0 ? 2 : buf - 1, k + 2, nc);
-      __syncthreads();
-      buf = buf == 2 ? 0 : buf + 1;
     }
-    __syncthreads();
-    if (tid == 0) s_ncand = 0;
-    __syncthreads();
+    wave_lds_sync();  // s_sup is rewritten by the next round
   }
-  flush();
+  if (nc) products(nc);
+  if (qn) drain(qn);
+  // D: results of the rows with an accepted centroid
+  if (!MULTI) {
+    const unsigned long long best = s_best[wave][lane];
+    if (wbase + lane < n && best != NO_KEY) {
+      const int32_t f = s_idx[wave][lane];
+      if (BATCH) {
+        const int64_t o = (int64_t)s_sub[wave][lane] * job.na + job.atlas;
+        write_result(best, job.bid, job.out_lab[o] + f, job.out_dst[o] + f, mt.flags);
+      } else {
+        write_result(best, job.bid, job.labels + f, job.dists + f, mt.flags);
+      }
+    }
+  }
 }
 
 int grow(void** p, size_t* have, size_t want) {
@@ -959,11 +999,10 @@ int grow(void** p, size_t* have, size_t want) {
 }
 
 // Stable sort of n keys (15 bits) into a permutation: vals_b[k] = index of
-// the k-th smallest key, and with `pay_in`, pay_out[k] = pay_in[vals_b[k]]
-// (64-byte records).  keys_a holds the keys on entry; keys_b, vals_a, vals_b
-// and hist (RS_BINS * nblocks + RS_BINS) are scratch.
+// the k-th smallest key.  keys_a holds the keys on entry; keys_b, vals_a,
+// vals_b and hist (RS_BINS * nblocks + RS_BINS) are scratch.
 int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, int32_t* vals_b,
-               uint32_t* hist, const uint4* pay_in, uint4* pay_out, hipStream_t s) {
+               uint32_t* hist, hipStream_t s) {
   if (n <= 0) return 0;
   const int32_t nblocks = (int32_t)((n + RS_IPB - 1) / RS_IPB);
   uint32_t* tot = hist + (size_t)RS_BINS * nblocks;
@@ -974,16 +1013,32 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
     rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, shift, hist, nblocks);
     rs_scan_rows_kernel<<<RS_BINS, RS_THREADS, 0, s>>>(hist, nblocks, tot);
     if (pass == 0)
-      rs_scatter_kernel<false><<<nblocks, RS_THREADS, 0, s>>>(
-          keys_a, nullptr, n, shift, hist, tot, nblocks, keys_b, vals_a, nullptr, nullptr);
-    else if (pay_in)
-      rs_scatter_kernel<true><<<nblocks, RS_THREADS, 0, s>>>(
-          keys_b, vals_a, n, shift, hist, tot, nblocks, nullptr, vals_b, pay_in, pay_out);
+      rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_a, nullptr, n, shift, hist, tot,
+                                                       nblocks, keys_b, vals_a);
     else
-      rs_scatter_kernel<false><<<nblocks, RS_THREADS, 0, s>>>(
-          keys_b, vals_a, n, shift, hist, tot, nblocks, nullptr, vals_b, nullptr, nullptr);
+      rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_b, vals_a, n, shift, hist, tot,
+                                                       nblocks, nullptr, vals_b);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Sort scratch for up to nk keys: keys (two buffers), values (two buffers;
+// the second is the permutation) and the digit counts.
+int grow_sort(PrefilterBuf& pb, int64_t nk) {
+  const int64_t nblocks = (nk + RS_IPB - 1) / RS_IPB;
+  int rc = grow(&pb.keys, &pb.keys_bytes, (size_t)nk * 2 * sizeof(uint32_t));
+  rc = rc ? rc : grow(&pb.vals, &pb.vals_bytes, (size_t)nk * 2 * sizeof(int32_t));
+  rc = rc ? rc : grow(&pb.hist, &pb.hist_bytes, (size_t)RS_BINS * (nblocks + 1) * 4);
+  return rc;
+}
+
+// Centroid order: cell keys of the prepared records, then the sort.
+int sort_centroids(const float* cprep, int32_t m, const PfParams* prm, PrefilterBuf& pb, int64_t nk,
+                   int32_t* cperm, hipStream_t s) {
+  uint32_t* keys_a = (uint32_t*)pb.keys;
+  int32_t* vals_a = (int32_t*)pb.vals;
+  cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
+  return radix_sort(m, keys_a, keys_a + nk, vals_a, cperm, (uint32_t*)pb.hist, s);
 }
 
 template <int Q>
@@ -992,32 +1047,19 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
                 PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo,
                 const int32_t* cperm_cached) {
   constexpr int EB = QTraits<Q>::bytes;
-  const int64_t n_pad = (n + 255) / 256 * 256;
   const int32_t ncols_pad = (m + 31) / 32 * 32;
   const int32_t ntiles = ncols_pad / 32;
   const int64_t nk = std::max<int64_t>(std::max<int64_t>(n, m), 1);  // sort capacity
-  const int64_t nblocks = (nk + RS_IPB - 1) / RS_IPB;
-  const int64_t nwaves = n_pad / 64;
-  // scratch: fiber payloads (input order), sort state, columns
-  // and tile boxes, per-fiber keys, per-wave survivor lists
-  const size_t pay_bytes = (size_t)n * PAY_WORDS * sizeof(uint4);
-  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, pay_bytes);
-  rc = rc ? rc : grow(&pb.keys, &pb.keys_bytes, (size_t)nk * 2 * sizeof(uint32_t));
-  rc = rc ? rc : grow(&pb.vals, &pb.vals_bytes, (size_t)nk * 2 * sizeof(int32_t));
-  rc = rc ? rc : grow(&pb.hist, &pb.hist_bytes, (size_t)RS_BINS * (nblocks + 1) * 4);
+  // scratch: fiber payloads (input order), sort state (keys, the fiber
+  // permutation), the centroid order, columns and tile boxes
+  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)n * PAY_WORDS * sizeof(uint4));
+  rc = rc ? rc : grow_sort(pb, nk);
   rc = rc ? rc : grow(&pb.cperm, &pb.cperm_bytes, (size_t)std::max<int32_t>(m, 1) * 4);
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
                       (size_t)ncols_pad * (KPC * EB + 2 * sizeof(float)));
-  rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes, (size_t)TROWS * ntiles * sizeof(float));
-  rc = rc ? rc : grow(&pb.fkeys, &pb.fkeys_bytes, (size_t)(n + 1) * sizeof(unsigned long long));
-  // shared overflow list (its counter sits after the per-fiber keys): 32
-  // entries per fiber (256 bytes, a fiber record's size), enough for the
-  // loose fp8 bound on large subjects (19 survivors per fiber at 10M x 20k)
-  const int64_t ovf_cap = std::min<int64_t>(std::max<int64_t>(32 * n, (int64_t)1 << 20),
-                                            (int64_t)1 << 30);
-  rc = rc ? rc : grow(&pb.list, &pb.list_bytes,
-                      (size_t)nwaves * (CULL_QCAP * sizeof(int2) + sizeof(uint32_t)) +
-                          (size_t)ovf_cap * sizeof(int2));
+  const int32_t nsuper = (ncols_pad + 255) / 256;  // one column block each
+  rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes,
+                      (size_t)TROWS * (ntiles + nsuper) * sizeof(float));
   if (rc) return rc;
   if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
   PfParams* prm = (PfParams*)pb.emax;
@@ -1026,62 +1068,174 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
   int32_t* ccent = (int32_t*)(cbias + ncols_pad);
   uint32_t* keys_a = (uint32_t*)pb.keys;
-  uint32_t* keys_b = keys_a + nk;
   int32_t* vals_a = (int32_t*)pb.vals;
-  int32_t* vals_b = vals_a + nk;
+  int32_t* perm = vals_a + nk;
   int32_t* cperm = (int32_t*)pb.cperm;
-  uint32_t* hist = (uint32_t*)pb.hist;
   if (launch_pf_setup(prm, cprep, m, s)) return -1;
-  // fibers: payloads and cell keys in input order, then the sort
-  unsigned long long* fkeys = (unsigned long long*)pb.fkeys;
-  unsigned long long* ovf_count = fkeys + n;
+  // centroids: their order (unless the prepared atlas holds it)
+  if (!cperm_cached && sort_centroids(cprep, m, prm, pb, nk, cperm, s)) return -1;
+  // fibers: payloads and cells in input order, then the permutation
   {
-    const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK, g = cf_grid<Q>();
-    cull_fiber_kernel<Q><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(fibers, n, prm, pay,
-                                                                          keys_a, fkeys);
+    const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK;
+    const FiberOut fo{pay, keys_a, mo ? nullptr : labels, mo ? nullptr : dists, nullptr, 0, 0,
+                      nullptr, nullptr, 0};
+    if (mt.flags & MF_TN) {
+      const int64_t g = cf_grid<Q, false, true>();
+      cull_fiber_kernel<Q, false, true><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(
+          fibers, n, prm, fo);
+    } else {
+      const int64_t g = cf_grid<Q, false, false>();
+      cull_fiber_kernel<Q, false, false><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(
+          fibers, n, prm, fo);
+    }
   }
-  if (radix_sort(n, keys_a, keys_b, vals_a, vals_b, hist, nullptr, nullptr, s)) return -1;
-  // centroids: cell keys and sort (unless the prepared atlas holds the
-  // order), then sorted columns with tile boxes
-  if (m > 0 && !cperm_cached) {
-    cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
-    if (radix_sort(m, keys_a, keys_b, vals_a, cperm, hist, nullptr, nullptr, s)) return -1;
-  }
-  cull_column_kernel<Q><<<(unsigned)((ncols_pad + 255) / 256), 256, 0, s>>>(
-      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent,
-      (float*)pb.tbox);
-  fill_u64_n_kernel<<<1, 64, 0, s>>>(ovf_count, 1, 0ull);
-  int2* list = (int2*)pb.list;
-  int2* ovf = list + nwaves * CULL_QCAP;
-  uint32_t* list_n = (uint32_t*)(ovf + ovf_cap);
-  const CullJob job{pay, vals_b, prm, cfeat, cbias, ccent, (const float*)pb.tbox, ntiles, fibers,
-                    n, cprep, fkeys, list, list_n, ovf, ovf_count, ovf_cap};
-  const unsigned blocks = (unsigned)(n_pad / 256);
+  if (radix_sort(n, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, s)) return -1;
+  // sorted columns with tile boxes
+  float* tbox = (float*)pb.tbox;
+  float* sbox = tbox + (size_t)TROWS * ntiles;
+  cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, s>>>(
+      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent, tbox,
+      sbox);
+  const CullJob job{pay,    perm,  prm,     cfeat,   cbias,   ccent, tbox, sbox, ntiles,
+                    nsuper, fibers, n,      cprep,   bid,     labels,  dists, nullptr, nullptr,
+                    nullptr, 0, 0};
+  const MultiOut mout = mo ? *mo : MultiOut{nullptr, 0, nullptr, nullptr};
+  const unsigned blocks = (unsigned)((n + 64 * CW - 1) / (64 * CW));
   if (ev && hipEventRecord(ev[0], s) != hipSuccess) return -1;
   if (counters)
-    cull_kernel<Q, true><<<blocks, 256, 0, s>>>(job, counters);
+    mo ? cull_kernel<Q, true, true, false><<<blocks, 64 * CW, 0, s>>>(job, mt, mout, counters)
+       : cull_kernel<Q, true, false, false><<<blocks, 64 * CW, 0, s>>>(job, mt, mout, counters);
   else
-    cull_kernel<Q, false><<<blocks, 256, 0, s>>>(job, counters);
+    mo ? cull_kernel<Q, false, true, false><<<blocks, 64 * CW, 0, s>>>(job, mt, mout, counters)
+       : cull_kernel<Q, false, false, false><<<blocks, 64 * CW, 0, s>>>(job, mt, mout, counters);
   if (ev && hipEventRecord(ev[1], s) != hipSuccess) return -1;
-  const MultiOut mout = mo ? *mo : MultiOut{nullptr, 0, nullptr, nullptr};
-  auto exact = [&](auto stats, auto multi) {
-    constexpr bool ST = decltype(stats)::value, MU = decltype(multi)::value;
-    exact_list_kernel<ST, CULL_QCAP, MU><<<blocks, 256, 0, s>>>(
-        list, list_n, nwaves, ovf, ovf_count, ovf_cap, vals_b, n, fibers, cprep, fkeys, counters,
-        mt, mout);
-    rescue_kernel<ST, MU><<<blocks < 1024u ? blocks : 1024u, 256, 0, s>>>(
-        list_n, nwaves, vals_b, n, fibers, cprep, m, fkeys, counters, mt, mout);
-  };
-  using T = std::true_type;
-  using F = std::false_type;
-  if (counters)
-    mo ? exact(T{}, T{}) : exact(T{}, F{});
-  else
-    mo ? exact(F{}, T{}) : exact(F{}, F{});
-  if (!mo)
-    finalize_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fkeys, n, bid, labels, dists,
-                                                                mt.flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// A batch of subjects against prepared atlases: the payloads, cells and
+// cells of every subject's fibers in one launch (one frame over the union of
+// the atlas boxes), one sort of all rows together (fibers of every subject
+// share the cells), then per atlas its columns and one culled pass over all
+// rows, each row writing its subject's output for that atlas.  The launches
+// are captured once per launch shape into a HIP graph and replayed.
+template <int Q>
+int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cperms,
+                      const float* const* fibers, const int64_t* nf, int32_t ns,
+                      int32_t* const* labels, float* const* dists, int mflags, PrefilterBuf& pb,
+                      BatchBuf& bb, hipStream_t s) {
+  constexpr int EB = QTraits<Q>::bytes;
+  // subjects with fibers, in order, and their outputs
+  std::vector<SubDev> subs;
+  std::vector<int32_t*> olab;
+  std::vector<float*> odst;
+  int64_t rows = 0, blk = 0;
+  for (int32_t i = 0; i < ns; ++i) {
+    if (nf[i] <= 0) continue;
+    subs.push_back(SubDev{fibers[i], nf[i], rows, blk});
+    for (int32_t a = 0; a < na; ++a) {
+      olab.push_back(labels[i * na + a]);
+      odst.push_back(dists[i * na + a]);
+    }
+    rows += nf[i];
+    blk += (nf[i] + CF_BLOCK - 1) / CF_BLOCK;
+  }
+  if (rows == 0) return 0;
+  if (rows >= ((int64_t)1 << 31)) return -4;  // sorted rows are indexed with 32 bits
+  const int32_t nsub = (int32_t)subs.size();
+  int32_t mmax = 1;
+  for (int32_t a = 0; a < na; ++a) mmax = std::max(mmax, at[a].m);
+  const int32_t cpad_max = (mmax + 31) / 32 * 32;
+  const int32_t tiles_max = cpad_max / 32;
+  const int32_t super_max = (cpad_max + 255) / 256;
+  const int64_t nk = std::max<int64_t>(rows, mmax);
+  // scratch (allocated before any capture)
+  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)rows * PAY_WORDS * sizeof(uint4));
+  rc = rc ? rc : grow_sort(pb, nk);
+  rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
+                      (size_t)cpad_max * (KPC * EB + 2 * sizeof(float)));
+  rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes,
+                      (size_t)TROWS * (tiles_max + super_max) * sizeof(float));
+  const size_t tab = (size_t)nsub * sizeof(SubDev) + olab.size() * 2 * sizeof(void*);
+  rc = rc ? rc : grow(&bb.citems, &bb.citems_bytes, tab);
+  if (rc) return rc;
+  if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
+  // the subject table (uploaded when it changed)
+  std::vector<uint64_t> tkey;
+  for (const SubDev& d : subs) {
+    tkey.push_back((uint64_t)(uintptr_t)d.fibers);
+    tkey.push_back((uint64_t)d.n);
+  }
+  for (size_t k = 0; k < olab.size(); ++k) {
+    tkey.push_back((uint64_t)(uintptr_t)olab[k]);
+    tkey.push_back((uint64_t)(uintptr_t)odst[k]);
+  }
+  SubDev* dsubs = (SubDev*)bb.citems;
+  int32_t** dlab = (int32_t**)(dsubs + nsub);
+  float** ddst = (float**)(dlab + olab.size());
+  if (bb.ckey != tkey || bb.citems_tab != bb.citems) {
+    std::vector<uint8_t> host(tab);
+    memcpy(host.data(), subs.data(), (size_t)nsub * sizeof(SubDev));
+    memcpy(host.data() + (size_t)nsub * sizeof(SubDev), olab.data(), olab.size() * sizeof(void*));
+    memcpy(host.data() + (size_t)nsub * sizeof(SubDev) + olab.size() * sizeof(void*), odst.data(),
+           odst.size() * sizeof(void*));
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(bb.citems, host.data(), tab, hipMemcpyHostToDevice) != hipSuccess)
+      return -1;
+    bb.ckey = tkey;
+    bb.citems_tab = bb.citems;
+  }
+  PfParams* prm = (PfParams*)pb.emax;
+  uint4* pay = (uint4*)pb.fib_feat;
+  uint8_t* cfeat = (uint8_t*)pb.cen_feat;
+  uint32_t* keys_a = (uint32_t*)pb.keys;
+  int32_t* vals_a = (int32_t*)pb.vals;
+  int32_t* perm = vals_a + nk;
+  float* tbox = (float*)pb.tbox;
+  const bool tn = (mflags & MF_TN) != 0;
+  const int64_t g = tn ? cf_grid<Q, true, true>() : cf_grid<Q, true, false>();
+  auto enqueue = [&](hipStream_t cs) -> int {
+    launch_pf_init(prm, cs);
+    for (int32_t a = 0; a < na; ++a) launch_pf_bbox_acc(prm, at[a].cprep, at[a].m, cs);
+    const FiberOut fo{pay, keys_a, nullptr, nullptr, dsubs, nsub, blk, dlab, ddst, na};
+    const unsigned grid = (unsigned)(blk < g ? blk : g);
+    if (tn)
+      cull_fiber_kernel<Q, true, true><<<grid, CF_BLOCK, 0, cs>>>(nullptr, 0, prm, fo);
+    else
+      cull_fiber_kernel<Q, true, false><<<grid, CF_BLOCK, 0, cs>>>(nullptr, 0, prm, fo);
+    if (radix_sort(rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs)) return -1;
+    for (int32_t a = 0; a < na; ++a) {
+      const int32_t m = at[a].m;
+      if (m <= 0) continue;  // every output already holds (-1, +inf)
+      const int32_t ncols_pad = (m + 31) / 32 * 32;
+      const int32_t ntiles = ncols_pad / 32;
+      const int32_t nsuper = (ncols_pad + 255) / 256;
+      float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
+      int32_t* ccent = (int32_t*)(cbias + ncols_pad);
+      float* sbox = tbox + (size_t)TROWS * ntiles;
+      cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(at[a].cprep, m, ncols_pad, cperms[a],
+                                                             prm, cfeat, cbias, ccent, tbox, sbox);
+      const CullJob job{pay,   perm,  prm,     cfeat, cbias, ccent, tbox, sbox, ntiles,
+                        nsuper, nullptr, rows, at[a].cprep, at[a].bid, nullptr, nullptr, dsubs,
+                        dlab,  ddst,  na,      a};
+      const MultiOut mout{nullptr, 0, nullptr, nullptr};
+      cull_kernel<Q, false, false, true>
+          <<<(unsigned)((rows + 64 * CW - 1) / (64 * CW)), 64 * CW, 0, cs>>>(
+              job, Metric{at[a].cext, mflags}, mout, nullptr);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  };
+  std::vector<uint64_t> key = {3u, (uint64_t)Q, (uint64_t)na, (uint64_t)mflags, (uint64_t)rows,
+                               (uint64_t)(uintptr_t)pb.fib_feat, (uint64_t)(uintptr_t)pb.keys,
+                               (uint64_t)(uintptr_t)pb.vals, (uint64_t)(uintptr_t)pb.hist,
+                               (uint64_t)(uintptr_t)pb.cen_feat, (uint64_t)(uintptr_t)pb.tbox,
+                               (uint64_t)(uintptr_t)pb.emax, (uint64_t)(uintptr_t)bb.citems};
+  for (int32_t a = 0; a < na; ++a) {
+    key.push_back((uint64_t)(uintptr_t)at[a].cprep);
+    key.push_back((uint64_t)at[a].m);
+    key.push_back((uint64_t)(uintptr_t)cperms[a]);
+  }
+  key.insert(key.end(), tkey.begin(), tkey.end());
+  return graph_launch(bb, key, s, enqueue);
 }
 
 }  // namespace
@@ -1100,23 +1254,28 @@ int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t 
   }
 }
 
+int run_cull_batch(int q, const BatchAtlas* atlases, int32_t n_atlases,
+                   const int32_t* const* cperms, const float* const* fibers,
+                   const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
+                   float* const* dists, int mflags, PrefilterBuf& pb, BatchBuf& bb,
+                   hipStream_t s) {
+  switch (q) {
+    case 0: return cull_batch_launch<Q_BF16>(atlases, n_atlases, cperms, fibers, n_fibers, n_subjects, labels, dists, mflags, pb, bb, s);
+    case 1: return cull_batch_launch<Q_F16>(atlases, n_atlases, cperms, fibers, n_fibers, n_subjects, labels, dists, mflags, pb, bb, s);
+    case 2: return cull_batch_launch<Q_FP8>(atlases, n_atlases, cperms, fibers, n_fibers, n_subjects, labels, dists, mflags, pb, bb, s);
+    default: return -2;
+  }
+}
+
 int cull_sort_centroids(const float* cprep, int32_t m, int32_t* cperm_out, PrefilterBuf& pb,
                         hipStream_t s) {
   if (m <= 0) return 0;
-  const int64_t nblocks = (m + RS_IPB - 1) / RS_IPB;
-  int rc = grow(&pb.keys, &pb.keys_bytes, (size_t)m * 2 * sizeof(uint32_t));
-  rc = rc ? rc : grow(&pb.vals, &pb.vals_bytes, (size_t)m * 2 * sizeof(int32_t));
-  rc = rc ? rc : grow(&pb.hist, &pb.hist_bytes, (size_t)RS_BINS * (nblocks + 1) * 4);
+  int rc = grow_sort(pb, m);
   if (rc) return rc;
   if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
   PfParams* prm = (PfParams*)pb.emax;
-  uint32_t* keys_a = (uint32_t*)pb.keys;
-  int32_t* vals_a = (int32_t*)pb.vals;
   if (launch_pf_setup(prm, cprep, m, s)) return -1;
-  cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
-  if (radix_sort(m, keys_a, keys_a + m, vals_a, cperm_out, (uint32_t*)pb.hist, nullptr, nullptr, s))
-    return -1;
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return sort_centroids(cprep, m, prm, pb, m, cperm_out, s);
 }
 
 }  // namespace seg

@@ -38,10 +38,6 @@ struct PrefilterBuf {
   size_t hist_bytes = 0;
   void* cperm = nullptr;  // sorted column -> centroid
   size_t cperm_bytes = 0;
-  void* fkeys = nullptr;  // per-fiber argmin keys + the survivor-list counter
-  size_t fkeys_bytes = 0;
-  void* list = nullptr;   // survivor pairs for the exact stage
-  size_t list_bytes = 0;
 };
 
 struct PfParams;
@@ -62,6 +58,11 @@ struct BatchBuf {
   hipGraphExec_t exec = nullptr;
   std::vector<uint64_t> key;  // launch shape of `exec`
   int32_t njobs = 0;          // jobs in the uploaded list
+  // the tile-culled batch: subject table and output pointers on the device
+  void* citems = nullptr;
+  size_t citems_bytes = 0;
+  std::vector<uint64_t> ckey;    // what `citems` holds
+  void* citems_tab = nullptr;    // the buffer `ckey` was uploaded to
 };
 
 // A prepared atlas as the batch path sees it.
@@ -109,6 +110,11 @@ int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float
 // Frame set-up shared by the prefilter forms: reset the parameters and take
 // the bounding box of the atlas points (seg_prefilter.hip).
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
+// The same in parts: reset, then widen the box by the points of one atlas
+// (several atlases share a frame this way).
+int launch_pf_init(PfParams* prm, hipStream_t s);
+size_t pf_params_bytes();
+int launch_pf_bbox_acc(PfParams* prm, const float* cprep, int32_t m, hipStream_t s);
 
 // Sorted, tile-culled prefilter (seg_cull.hip); q: 0 bf16, 1 fp16, 2 fp8.
 // Returns as run_prefilter, and -4 for 2^31 fibers or more.
@@ -116,6 +122,14 @@ int run_cull(int q, const float* fibers, int64_t n, const float* cprep, int32_t 
              const int32_t* bid, int32_t* labels, float* dists, unsigned long long* counters,
              Metric mt, PrefilterBuf& pb, hipEvent_t* ev, hipStream_t s, const MultiOut* mo = nullptr,
              const int32_t* cperm = nullptr);
+// The tile-culled form for a batch: every subject's fibers sorted together,
+// then one culled pass per atlas (seg_cull.hip).  cperms[a] is atlas a's
+// centroid order (cull_sort_centroids).  Returns as run_cull.
+int run_cull_batch(int q, const BatchAtlas* atlases, int32_t n_atlases,
+                   const int32_t* const* cperms, const float* const* fibers,
+                   const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
+                   float* const* dists, int mflags, PrefilterBuf& pb, BatchBuf& bb,
+                   hipStream_t s);
 // The tile-culled form's centroid order for a prepared atlas: centroids
 // sorted by the cell of their center point in the atlas's frame (the same for
 // every subject and quantisation), written to cperm_out [m].
@@ -136,11 +150,5 @@ int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atla
 int plain_batch(int cfg, const BatchAtlas* atlases, int32_t n_atlases, const float* const* fibers,
                 const int64_t* n_fibers, int32_t n_subjects, int32_t* const* labels,
                 float* const* dists, int mflags, BatchBuf& bb, hipStream_t s);
-
-// Batched persistent launch (seg_batch.hip); same return codes.
-int run_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atlases,
-              const float* const* fibers, const int64_t* n_fibers, int32_t n_subjects,
-              int32_t* const* labels, float* const* dists, int mflags, BatchBuf& bb,
-              PrefilterBuf& pb, hipStream_t s);
 
 }  // namespace seg

@@ -31,6 +31,7 @@ template <> struct QTraits<Q_BF16> {
   static __device__ double dec(uint32_t b) {
     return (double)__uint_as_float(b << 16);
   }
+  static __device__ float decf(uint32_t b) { return __uint_as_float(b << 16); }
 };
 template <> struct QTraits<Q_F16> {
   static constexpr int bytes = 2;
@@ -42,6 +43,7 @@ template <> struct QTraits<Q_F16> {
   static __device__ double dec(uint32_t b) {
     return (double)__half2float(__ushort_as_half((unsigned short)b));
   }
+  static __device__ float decf(uint32_t b) { return __half2float(__ushort_as_half((unsigned short)b)); }
 };
 // OCP e4m3 (bias 7, no infinities, max 448), round to nearest even, saturating.
 template <> struct QTraits<Q_FP8> {
@@ -70,6 +72,13 @@ template <> struct QTraits<Q_FP8> {
     const uint32_t E = (b >> 3) & 0xFu, mnt = b & 7u;
     if (E == 0) return sg * mnt * (1.0 / 512.0);
     return sg * (1.0 + mnt / 8.0) * ldexp(1.0, (int)E - 7);
+  }
+  // the same value in float (exact: at most 4 significant bits)
+  static __device__ float decf(uint32_t b) {
+    const float sg = (b & 0x80u) ? -1.0f : 1.0f;
+    const uint32_t E = (b >> 3) & 0xFu, mnt = b & 7u;
+    if (E == 0) return sg * ldexpf((float)mnt, -9);
+    return sg * ldexpf((float)(8u + mnt), (int)E - 10);
   }
 };
 

@@ -758,6 +758,18 @@ int prefilter_batch(int mode, int cfg, const BatchAtlas* atlases, int32_t n_atla
                         dists, mflags, bb, s);
 }
 
+size_t pf_params_bytes() { return sizeof(PfParams); }
+
+int launch_pf_init(PfParams* prm, hipStream_t s) {
+  pf_init_kernel<<<1, 64, 0, s>>>(prm);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pf_bbox_acc(PfParams* prm, const float* cprep, int32_t m, hipStream_t s) {
+  launch_pf_bbox(cprep, m, prm, s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_pf_setup(PfParams* prm, const float* cprep, int32_t m, hipStream_t s) {
   pf_init_kernel<<<1, 64, 0, s>>>(prm);
   if (m > 0) launch_pf_bbox(cprep, m, prm, s);

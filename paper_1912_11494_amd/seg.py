@@ -90,6 +90,8 @@ def lib():
                                           ctypes.POINTER(Options), P]
         L.seg_segment_noalloc.restype = ctypes.c_int
         L.seg_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.seg_scratch_bytes.argtypes = [P]
+        L.seg_scratch_bytes.restype = i64
         L.seg_last_error.restype = ctypes.c_char_p
         L.seg_version.restype = ctypes.c_int
         L.seg_atlas_create.argtypes = [P, i64, P, P, i32, P, ctypes.POINTER(P)]
@@ -233,6 +235,11 @@ def segment_noalloc(fibers: torch.Tensor, centroids: torch.Tensor,
                                    _stream(stream))
     _check(rc)
     return labels, dists
+
+
+def scratch_bytes(stream=None) -> int:
+    """Device bytes of library scratch held for the current device and stream."""
+    return int(lib().seg_scratch_bytes(_stream(stream)))
 
 
 def query_stats() -> dict:

@@ -55,3 +55,37 @@ def test_traffic_table(tmp_path):
     assert abs(r["bytes_per_launch"] - (500.0 * 1024 * 2 + 70.0 * 1024)) < 1e-6
     assert r["source_hash"] == bench.source_hash()
     assert "cull_kernel:bf16" not in d
+
+
+def test_counter_table(tmp_path):
+    """Counter passes summarised per kernel: each counter averaged over the
+    kernel's dispatches, ratios derived from them, other kernels left out."""
+    cull = "void seg::(anonymous namespace)::cull_kernel<1, false, false, false>(seg::CullJob)"
+    stats = "void seg::(anonymous namespace)::cull_kernel<1, true, false, false>(seg::CullJob)"
+    p1, p2 = tmp_path / "a.csv", tmp_path / "b.csv"
+    with open(p1, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for d, v in ((1, 100.0), (2, 300.0)):
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": cull, "Counter_Name": "SQ_WAVES",
+                        "Counter_Value": 10.0})
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": cull, "Counter_Name": "SQ_WAVE_CYCLES",
+                        "Counter_Value": v})
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": cull, "Counter_Name": "SQ_WAIT_ANY",
+                        "Counter_Value": v / 2})
+        w.writerow({"Dispatch_Id": 3, "Kernel_Name": stats, "Counter_Name": "SQ_WAVES",
+                    "Counter_Value": 99.0})
+    with open(p2, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        w.writerow({"Dispatch_Id": 1, "Kernel_Name": cull, "Counter_Name": "SQ_INSTS_MFMA",
+                    "Counter_Value": 40.0})
+    out = bench.write_counters([str(p1), str(p2)], str(tmp_path / "c.json"))
+    c = out["cull_kernel:fp16"]
+    assert c["counters"]["SQ_WAVE_CYCLES"] == 200.0
+    assert abs(c["derived"]["wait_any_frac"] - 0.5) < 1e-12
+    assert abs(c["derived"]["wave_cycles_per_wave"] - 20.0) < 1e-12
+    assert abs(c["derived"]["insts_mfma_per_wave"] - 4.0) < 1e-12
+    assert set(out) == {"cull_kernel:fp16"}

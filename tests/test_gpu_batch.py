@@ -129,6 +129,53 @@ def test_batch_graph_replay_and_reshape(seg):
             assert np.array_equal(outs3[i][a][0].cpu().numpy(), l32)
 
 
+@pytest.mark.parametrize("mode", ["fp16", "fp8"])
+def test_batch_culled_graph_replay(seg, mode):
+    """The tile-culled batch (all subjects sorted together, one culled pass per
+    atlas) replayed from its cached graph: outputs overwritten between replays,
+    eager calls in between, then new fibers in the same buffers, then another
+    subject layout (a new capture); every result equals the oracle's."""
+    import torch
+
+    atl = _atlases()
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    subs = _subjects(atl, [700, 2100, 333], seed=41)
+    gf = [torch.from_numpy(f).to(d) for f in subs]
+    outs = [[(torch.empty(len(f), dtype=torch.int32, device=d),
+              torch.empty(len(f), dtype=torch.float32, device=d)) for _ in atl] for f in subs]
+
+    def check(cases, outs, ctx):
+        for i, f in enumerate(cases):
+            for a, at in enumerate(atl):
+                l32, d32, _ = oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)
+                assert np.array_equal(outs[i][a][0].cpu().numpy(), l32), (ctx, i, a)
+                assert np.array_equal(outs[i][a][1].cpu().numpy(), d32), (ctx, i, a)
+
+    for rep in range(3):
+        log(f"culled batch {mode} replay {rep}")
+        for o in outs:
+            for lab, dist in o:
+                lab.fill_(-7)
+                dist.fill_(-7.0)
+        seg.segment_batch(ga, gf, mode=mode, outs=outs)
+        torch.cuda.synchronize()
+        l_e, _ = ga[1].segment(gf[1], mode=mode)  # eager work between replays
+        torch.cuda.synchronize()
+        check(subs, outs, f"replay {rep}")
+    new = _subjects(atl, [700, 2100, 333], seed=42)
+    for g, f in zip(gf, new):
+        g.copy_(torch.from_numpy(f).to(d))
+    seg.segment_batch(ga, gf, mode=mode, outs=outs)
+    torch.cuda.synchronize()
+    check(new, outs, "new data")
+    subs3 = _subjects(atl, [0, 129, 4000, 1], seed=43)
+    gf3 = [torch.from_numpy(f).to(d) for f in subs3]
+    outs3 = seg.segment_batch(ga, gf3, mode=mode)
+    torch.cuda.synchronize()
+    check(subs3, outs3, "new layout")
+
+
 def test_batch_empty_atlas(seg):
     import torch
 

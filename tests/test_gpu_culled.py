@@ -105,8 +105,9 @@ def test_culled_special_thresholds(seg, mode):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_culled_every_tile_hits(seg, mode):
-    """Thresholds far above every distance: nothing can be skipped, two rounds
-    of 256 tiles (9,000 centroids), many queue drains."""
+    """Thresholds far above every distance: nothing can be skipped (282 tiles
+    of 9,000 centroids: more candidates than one candidate list holds), many
+    queue drains."""
     fib, at = synth.small_case(300, 90, 100, seed=21)
     thr = np.full(at.n_bundles, 1000.0, np.float32)
     log(f"culled all-hit mode={mode}")
@@ -115,17 +116,20 @@ def test_culled_every_tile_hits(seg, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_culled_overflow_list(seg, mode):
-    """Wide thresholds: each wave of 64 fibers has more survivors than its own
-    part of the survivor list holds, so the shared overflow list is used."""
+def test_culled_many_drains(seg, mode):
+    """Wide thresholds: each wave of 64 fibers has far more survivors than its
+    queue holds between two products (256 entries), so the exact stage runs
+    several times per wave in the middle of the candidate loop."""
     fib, at = synth.small_case(4000, 20, 100, seed=22, len_lo=20.0, len_hi=60.0)
     thr = (at.thresholds * 4.0).astype(np.float32)
-    log(f"culled overflow mode={mode}")
-    _, _, st = _check(seg, fib, at.centroids, at.bundle_id, thr, mode, f"culled overflow {mode}",
+    log(f"culled many drains mode={mode}")
+    _, _, st = _check(seg, fib, at.centroids, at.bundle_id, thr, mode, f"culled drains {mode}",
                       check_f64=False)
-    per_wave = st["filter_pass"] / ((len(fib) + 63) // 64)
-    log(f"  survivors per wave {per_wave:.0f}")
+    waves = (len(fib) + 63) // 64
+    per_wave = st["filter_pass"] / waves
+    log(f"  survivors per wave {per_wave:.0f}, drains per wave {st['drains'] / waves:.1f}")
     assert per_wave > 512
+    assert st["drains"] > waves  # some waves drained in the middle of the loop
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -160,7 +164,9 @@ def test_culled_matches_streaming(seg):
 @pytest.mark.parametrize("mode", MODES)
 def test_culled_prepared_atlas_order(seg, mode):
     """A prepared atlas keeps its tile-culled centroid order from creation; its
-    calls equal the one-shot call, down to the culling statistics."""
+    calls equal the one-shot call.  Items of one cell are sorted in no fixed
+    order, so the survivor counts (which depend on the grouping) may differ
+    between calls; the accepted pairs may not."""
     import torch
 
     fib, at = synth.small_case(12000, 25, 40, seed=38, len_lo=20.0, len_hi=80.0)
@@ -174,6 +180,6 @@ def test_culled_prepared_atlas_order(seg, mode):
         s2 = seg.query_stats()
         torch.cuda.synchronize()
         assert torch.equal(l1, l2) and torch.equal(d1, d2)
-        assert s1 == s2
+        assert (s1["pairs"], s1["accepted"]) == (s2["pairs"], s2["accepted"])
     assert_parity(l2.cpu().numpy(), d2.cpu().numpy(), fib, at.centroids, at.bundle_id,
                   at.thresholds, ctx=f"prepared {mode}", check_f64=False)

@@ -127,7 +127,8 @@ def test_multi_capacity_and_slots(seg):
 @pytest.mark.parametrize("mode", MODES)
 def test_multi_all_bundles(seg, mode):
     """Infinite thresholds: every fiber in every bundle (16 bundles, 16 slots);
-    every tile passes, many waves take the rescue path."""
+    every tile passes and every pair survives, so each wave drains its queue
+    many times."""
     fib, at = synth.small_case(600, 16, 30, seed=34)
     thr = np.full(16, np.inf, np.float32)
     want = oracle.segment_multi_f32(fib, at.centroids, at.bundle_id, thr)
