@@ -24,9 +24,10 @@
 // scatters with ranks from wave ballots, so equal keys keep their input
 // order and the permutation is deterministic.
 //
-// Fiber payloads (feature codes, row constant, error bound, input index,
-// arc length) are computed in input order with coalesced reads of the
-// records; the culled kernel reads its rows through the permutation.
+// Fiber payloads (feature codes, row constant, error bound; arc length and
+// subject where needed) are computed in input order, four lanes per fiber,
+// and written as whole memory lines; the culled kernel gathers its rows
+// through the permutation.
 //
 // Work per wave (64 consecutive sorted rows = 2 groups of 32; the four
 // waves of a block run independently):
@@ -266,85 +267,128 @@ __global__ __launch_bounds__(256) void cell_key_kernel(const float* __restrict__
   if (i < n) keys[i] = center_cell(recs + i * stride, prm);
 }
 
-// Per-fiber payload, 64 bytes (4 x uint4), written in input order:
-//   words 0-1  the quantised feature codes (16 codes; fp8 uses word 0)
-//   word 2     (-Ha, error bound |Xq - X|, input index, arc length)
-//   word 3     not written, not read
+// Per-fiber payload in input (row) order, as arrays that the fiber kernel
+// writes whole (a partial memory line costs a read-modify-write) and the
+// culled kernel gathers a row at a time (two 64-byte sectors per row):
+//   codes  the 16 quantised feature codes, 16 x the code size
+//   rec    the row constants: (-Ha, error bound |Xq - X|), 8 bytes; with the
+//          length-normalised metric or in a batch (`wide`) 16 bytes,
+//          (-Ha, error bound, arc length, 0) or (-Ha, error bound, subject,
+//          index within the subject)
+//   len    the arc length of a batch row (length-normalised metric)
 // A fiber with a non-finite coordinate gets -Ha = +inf (it bypasses the cut),
-// error bound +inf (its box is unbounded) and zero codes.  The arc length
-// (the length-normalised metric) is that of arc_length, else 0.
-constexpr int PAY_WORDS = 4;
+// error bound +inf (its box is unbounded) and zero codes.  The arc length is
+// that of arc_length.
+struct Payload {
+  uint8_t* codes;
+  void* rec;
+  float* len;
+  int wide;
+};
+constexpr size_t PAY_BYTES = 32 + 16 + 4;  // per row, the largest layout
 
-// One lane per fiber: a block takes batches of CF_BLOCK fibers (grid-stride,
-// as many blocks as the device holds at once);
-// a batch's contiguous records (CF_BLOCK x 252 bytes) come in with coalesced
-// 16-byte loads into registers, go to LDS, and the loads of the block's next
-// batch are issued before the lanes quantise the current one, each its own
-// record from LDS (a stride of 63 words, no bank conflict), and write its
-// payload and its cell key, and writes the empty result (-1, +inf) of the
-// fiber when `labels` is not null.
+// The payload arrays carved from one allocation of rows * PAY_BYTES.
+inline Payload payload_of(void* base, int64_t rows, bool wide) {
+  Payload p;
+  p.codes = (uint8_t*)base;
+  p.rec = p.codes + (size_t)rows * 32;
+  p.len = (float*)((uint8_t*)p.rec + (size_t)rows * 16);
+  p.wide = wide ? 1 : 0;
+  return p;
+}
+
+// Four lanes per fiber (a quad); a block takes batches of CF_FIB fibers
+// (grid-stride, as many blocks as the device holds at once).  Lane s of the
+// quad loads and quantises feature group s of the symmetric map: s = 0 the
+// center point (features 0-2, and the zero feature 15), s = 1, 2, 3 the point
+// pairs (7, 13), (4, 16), (0, 20) (features 3-6, 7-10, 11-14), each feature
+// with the same double arithmetic as quantise_row.  The quad adds its partial
+// sums (|Xq|^2, |Xq - X|^2, |X|^2) with two lane permutations, the same sums
+// in every lane, and every lane derives the row constant and the error bound
+// from them; lane s then stores codes 4s .. 4s+3 (its own and the first of
+// lane s + 1), so the quad writes the code words whole.  The records are read
+// from memory directly: the wave's sixteen fibers are 4 KB in a row, and the
+// points the quad needs touch every line of them once.  Lane 0 writes the
+// cell key, lanes 1 and 2 the empty result (-1, +inf) when `labels` is not
+// null, lane 2 the constants word (and lane 3 the subject word of a batch).
+// With the length-normalised metric, every lane of the quad also reads the
+// whole record for its arc length.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));  // 16-byte aligned
-constexpr int CF_BLOCK = 128;
-constexpr int CF_V = (CF_BLOCK * NF / 4 + CF_BLOCK - 1) / CF_BLOCK;  // loads per lane
+// one point: exactly 12 bytes (a three-element vector type would load 16)
+struct Pt3 {
+  float x, y, z;
+};
+constexpr int CF_FIB = 64;              // fibers per block and batch
+constexpr int CF_THREADS = 4 * CF_FIB;  // four lanes each
 
 // One subject of a batch as the kernels see it.
 struct SubDev {
   const float* fibers;  // [n][21][3]
   int64_t n;
   int64_t row0;         // its first row among the rows of the batch
-  int64_t blk0;         // its first CF_BLOCK batch of the payload kernel
+  int64_t blk0;         // its first CF_FIB batch of the payload kernel
 };
 
 // Where the fibers of payload batch b come from.  One subject: fibers
-// [b * CF_BLOCK, ...) of `fibers`.  A batch of subjects (`subs`, ascending
-// blk0): the subject whose batches hold b, found by bisection.
+// [b * CF_FIB, ...) of `fibers`.  A batch of subjects (`subs`, ascending
+// blk0): subject `cur`, which the caller keeps current as b grows (SubCursor).
 struct BatchSrc {
   const float* src;  // first record
-  int cnt;           // records (at most CF_BLOCK)
+  int cnt;           // records (at most CF_FIB)
   int64_t row;       // row of the first record (payload, keys)
   int64_t local;     // index of the first record within its subject
   int32_t sub;       // subject
 };
 
-template <bool BATCH>
-__device__ __forceinline__ BatchSrc batch_src(int64_t b, const float* __restrict__ fibers,
-                                              int64_t n, const SubDev* __restrict__ subs,
-                                              int32_t nsub) {
-  BatchSrc r;
-  if (!BATCH) {
-    r.local = b * CF_BLOCK;
-    r.row = r.local;
-    r.sub = 0;
-    r.src = fibers + r.local * NF;
-    r.cnt = (int)(n - r.local < CF_BLOCK ? n - r.local : CF_BLOCK);
-  } else {
+// The subject of a growing batch index: found by bisection once, then
+// advanced one subject at a time (a block's batches only increase), so a
+// batch costs no dependent loads.
+struct SubCursor {
+  int32_t cur;
+  SubDev sd;
+  int64_t next;  // first batch of subject cur + 1
+
+  __device__ void seek(int64_t b, const SubDev* __restrict__ subs, int32_t nsub) {
     int32_t lo = 0, hi = nsub - 1;
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) >> 1;
       if (subs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
     }
-    const SubDev sd = subs[lo];
-    r.local = (b - sd.blk0) * CF_BLOCK;
-    r.row = sd.row0 + r.local;
-    r.sub = lo;
-    r.src = sd.fibers + r.local * NF;
-    r.cnt = (int)(sd.n - r.local < CF_BLOCK ? sd.n - r.local : CF_BLOCK);
+    set(lo, subs, nsub);
+  }
+  __device__ void set(int32_t c, const SubDev* __restrict__ subs, int32_t nsub) {
+    cur = c;
+    sd = subs[c];
+    next = c + 1 < nsub ? subs[c + 1].blk0 : INT64_MAX;
+  }
+  __device__ void advance(int64_t b, const SubDev* __restrict__ subs, int32_t nsub) {
+    while (b >= next) set(cur + 1, subs, nsub);
+  }
+};
+
+template <bool BATCH>
+__device__ __forceinline__ BatchSrc batch_src(int64_t b, const float* __restrict__ fibers,
+                                              int64_t n, const SubCursor& sc) {
+  BatchSrc r;
+  if (!BATCH) {
+    r.local = b * CF_FIB;
+    r.row = r.local;
+    r.sub = 0;
+    r.src = fibers + r.local * NF;
+    r.cnt = (int)(n - r.local < CF_FIB ? n - r.local : CF_FIB);
+  } else {
+    r.local = (b - sc.sd.blk0) * CF_FIB;
+    r.row = sc.sd.row0 + r.local;
+    r.sub = sc.cur;
+    r.src = sc.sd.fibers + r.local * NF;
+    r.cnt = (int)(sc.sd.n - r.local < CF_FIB ? sc.sd.n - r.local : CF_FIB);
   }
   return r;
 }
 
-__device__ __forceinline__ void cf_load(const BatchSrc& bs, int tid, f4u* v) {
-  const int n4 = (bs.cnt * NF) >> 2;
-#pragma unroll
-  for (int u = 0; u < CF_V; ++u) {
-    const int i = tid + u * CF_BLOCK;
-    if (i < n4) v[u] = *(const f4u*)(bs.src + 4 * i);
-  }
-}
-
 struct FiberOut {
-  uint4* pay;          // [rows][PAY_WORDS]
+  Payload pay;
   uint32_t* keys;      // [rows] cell
   int32_t* labels;     // one subject: [n] or null
   float* dists;        // one subject: [n] or null
@@ -357,86 +401,170 @@ struct FiberOut {
   int32_t na;
 };
 
+// Sum of a double over the four lanes of each quad (every lane gets the same
+// value: the two additions are commutative).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double quad_sum(double v) {
+  v = v + dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  return v + dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+}
+
 template <int Q, bool BATCH, bool TN>
-__global__ __launch_bounds__(CF_BLOCK) void cull_fiber_kernel(const float* __restrict__ fibers,
-                                                              int64_t n,
-                                                              PfParams* __restrict__ prm,
-                                                              FiberOut fo) {
-  __shared__ float s_rec[CF_BLOCK * NF];
+__global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __restrict__ fibers,
+                                                                int64_t n,
+                                                                PfParams* __restrict__ prm,
+                                                                FiberOut fo) {
+  using T = QTraits<Q>;
+  constexpr int EB = T::bytes;
+  constexpr int SIDE = 1 << CELL_AXIS_BITS;
   const int tid = (int)threadIdx.x;
-  const int64_t nb = BATCH ? fo.nblk : (n + CF_BLOCK - 1) / CF_BLOCK;
-  f4u v[CF_V];
-  int64_t b = blockIdx.x;
-  if (b < nb) cf_load(batch_src<BATCH>(b, fibers, n, fo.subs, fo.nsub), tid, v);
+  const int sl = tid & 3;   // feature group of this lane
+  const int fb = tid >> 2;  // fiber within the batch
+  const int64_t nb = BATCH ? fo.nblk : (n + CF_FIB - 1) / CF_FIB;
+  // the frame and the cell grid, once
+  const Frame fr = frame(prm, Q);
+  float clo[3], csc[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    clo[d] = unord(prm->lo[d]);
+    const float ext = unord(prm->hi[d]) - clo[d];
+    csc[d] = (float)SIDE / (ext > 0.0f ? ext : 1.0f);
+  }
+  // this lane's points: i and its partner 20 - i (the center point twice)
+  const int pi = sl == 0 ? CTR : SymGroups<KPC>::grp(sl);
+  const int pj = NP - 1 - pi;
+  const double g = gamma_acc(KPC);
   float e32 = 0.0f;
-  for (; b < nb; b += gridDim.x) {
-    const BatchSrc bs = batch_src<BATCH>(b, fibers, n, fo.subs, fo.nsub);
-    {
-      const int nfl = bs.cnt * NF;
-      const int n4 = nfl >> 2;
+  SubCursor cursor{};
+  if (BATCH && (int64_t)blockIdx.x < nb) cursor.seek(blockIdx.x, fo.subs, fo.nsub);
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    if (BATCH) cursor.advance(b, fo.subs, fo.nsub);
+    const BatchSrc bs = batch_src<BATCH>(b, fibers, n, cursor);
+    if (fb >= bs.cnt) continue;  // the whole quad
+    const float* rec = bs.src + (int64_t)fb * NF;
+    const Pt3 A = *(const Pt3*)(rec + 3 * pi);
+    const Pt3 B = *(const Pt3*)(rec + 3 * pj);
+    // features: the center point's coordinates, or a pair's midpoint and
+    // half distance (exactly as in `features`); lane 0's fourth is feature
+    // 15, zero
+    double x[4];
+    if (sl == 0) {
+      x[0] = (double)A.x - fr.o[0];
+      x[1] = (double)A.y - fr.o[1];
+      x[2] = (double)A.z - fr.o[2];
+      x[3] = 0.0;
+    } else {
+      double h2 = 0.0;
+      const float a3[3] = {A.x, A.y, A.z}, b3[3] = {B.x, B.y, B.z};
 #pragma unroll
-      for (int u = 0; u < CF_V; ++u) {
-        const int i = tid + u * CF_BLOCK;
-        if (i < n4) {
-          s_rec[4 * i] = v[u].x;
-          s_rec[4 * i + 1] = v[u].y;
-          s_rec[4 * i + 2] = v[u].z;
-          s_rec[4 * i + 3] = v[u].w;
-        }
+      for (int d = 0; d < 3; ++d) {
+        const double a = a3[d], bb = b3[d];
+        x[d] = 0.5 * (a + bb) - fr.o[d];
+        h2 += (a - bb) * (a - bb);
       }
-      if (tid < nfl - 4 * n4) s_rec[4 * n4 + tid] = bs.src[4 * n4 + tid];
+      x[3] = 0.5 * sqrt(h2);
     }
-    __syncthreads();
-    if (b + gridDim.x < nb)
-      cf_load(batch_src<BATCH>(b + gridDim.x, fibers, n, fo.subs, fo.nsub), tid, v);
-    const int64_t f = bs.row + tid;     // payload row
-    const int64_t loc = bs.local + tid;  // index within the subject
-    if (tid < bs.cnt) {
-      float rec[NF];
+    uint32_t c[4];
+    double nq = 0.0, err = 0.0, nx = 0.0;
 #pragma unroll
-      for (int k = 0; k < NF; ++k) rec[k] = s_rec[tid * NF + k];
-      fo.keys[f] = center_cell(rec, prm);
-      uint4* P = fo.pay + f * PAY_WORDS;
-      if (QTraits<Q>::bytes == 1) P[1] = make_uint4(0u, 0u, 0u, 0u);
-      double nq, e;
-      quantise_row<Q, MAP_SYM, KPC>(rec, false, prm, (uint8_t*)P, &nq, &e);
-      float nh, er;
-      if (!__builtin_isfinite(e)) {
-        nh = __builtin_inff();
-        er = __builtin_inff();
-      } else {
-        const double g = gamma_acc(KPC);
-        const double ha = (0.5 - g) * nq * (1.0 - 0x1p-40);  // round towards passing
-        nh = __double2float_ru(-ha * frame(prm, Q).s2);
-        er = __double2float_ru(e);
-        e32 = fmaxf(e32, er);
+    for (int k = 0; k < 4; ++k) {
+      c[k] = T::enc(x[k] * fr.s);
+      const double xq = T::dec(c[k]) * fr.is;  // exact (power-of-two scale)
+      nq += xq * xq;
+      err += (xq - x[k]) * (xq - x[k]);
+      nx += x[k] * x[k];
+    }
+    nq = quad_sum(nq);
+    err = quad_sum(err);
+    nx = quad_sum(nx);
+    const bool finite = __builtin_isfinite(err + nx + nq);
+    // codes 4 sl .. 4 sl + 3: lane 0 its own three and lane 1's first, lane
+    // s > 0 its last three and lane s + 1's first (lane 3: feature 15, zero)
+    const uint32_t nxt = (uint32_t)__builtin_amdgcn_mov_dpp((int)c[0], 0xF9, 0xF, 0xF, false);
+    uint32_t o0 = sl == 0 ? c[0] : c[1], o1 = sl == 0 ? c[1] : c[2];
+    uint32_t o2 = sl == 0 ? c[2] : c[3], o3 = sl == 3 ? 0u : nxt;
+    if (!finite) o0 = o1 = o2 = o3 = 0u;  // a bypassing row: zero codes
+    const int64_t f = bs.row + fb;     // payload row
+    const int64_t loc = bs.local + fb;  // index within the subject
+    uint8_t* C = fo.pay.codes + f * (16 * EB);
+    if (EB == 2)
+      *(uint2*)(C + 8 * sl) = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
+    else
+      *(uint32_t*)(C + 4 * sl) = o0 | (o1 << 8) | (o2 << 16) | (o3 << 24);
+    float nh, er;
+    if (!finite) {
+      nh = __builtin_inff();
+      er = __builtin_inff();
+    } else {
+      // the double features themselves (square roots) carry 2^-50 relative
+      // error
+      const double e = sqrt(err) * (1.0 + 0x1p-40) + 0x1p-50 * sqrt(nx) + 1e-30;
+      const double ha = (0.5 - g) * nq * (1.0 - 0x1p-40);  // round towards passing
+      nh = __double2float_ru(-ha * fr.s2);
+      er = __double2float_ru(e);
+      e32 = fmaxf(e32, er);
+    }
+    if (sl == 0) {
+      uint32_t code = 0;
+      const float a3[3] = {A.x, A.y, A.z};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float t = (a3[d] - clo[d]) * csc[d];
+        const int q = t >= 0.0f ? (t < (float)(SIDE - 1) ? (int)t : SIDE - 1) : 0;
+        code |= spread3((uint32_t)q) << d;
       }
-      // (a template flag, not a branch the compiler could turn into selects;
-      // from LDS: the record's registers are free by now)
-      const float len = TN ? arc_length(s_rec + tid * NF) : 0.0f;
-      P[2] = make_uint4(__float_as_uint(nh), __float_as_uint(er), (uint32_t)loc,
-                        __float_as_uint(len));
+      fo.keys[f] = code;
+    } else if (sl == 2) {
+      float len = 0.0f;
+      if (TN) {
+        float r[NF];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) {
+          const f4u v = *(const f4u*)(rec + 4 * k);
+          r[4 * k] = v.x;
+          r[4 * k + 1] = v.y;
+          r[4 * k + 2] = v.z;
+          r[4 * k + 3] = v.w;
+        }
+        r[60] = rec[60];
+        r[61] = rec[61];
+        r[62] = rec[62];
+        len = arc_length(r);
+      }
       if (BATCH) {
-        P[3] = make_uint4((uint32_t)bs.sub, 0u, 0u, 0u);
-        for (int32_t a = 0; a < fo.na; ++a) {
-          fo.out_lab[bs.sub * fo.na + a][loc] = -1;
-          fo.out_dst[bs.sub * fo.na + a][loc] = __builtin_inff();
-        }
-      } else if (fo.labels) {
-        fo.labels[f] = -1;
-        fo.dists[f] = __builtin_inff();
+        ((float4*)fo.pay.rec)[f] = make_float4(nh, er, __int_as_float(bs.sub),
+                                               __int_as_float((int32_t)loc));
+        if (TN) fo.pay.len[f] = len;
+      } else if (TN) {
+        ((float4*)fo.pay.rec)[f] = make_float4(nh, er, len, 0.0f);
+      } else {
+        ((float2*)fo.pay.rec)[f] = make_float2(nh, er);
       }
     }
-    __syncthreads();  // the records are read before the next batch lands
+    if (BATCH) {
+      if (sl == 1)
+        for (int32_t a = 0; a < fo.na; ++a) fo.out_lab[bs.sub * fo.na + a][loc] = -1;
+      else if (sl == 2)
+        for (int32_t a = 0; a < fo.na; ++a) fo.out_dst[bs.sub * fo.na + a][loc] = __builtin_inff();
+    } else if (fo.labels) {
+      if (sl == 1) fo.labels[f] = -1;
+      else if (sl == 2) fo.dists[f] = __builtin_inff();
+    }
   }
   for (int off = 32; off > 0; off >>= 1) e32 = fmaxf(e32, __shfl_xor(e32, off));
   if ((tid & 63) == 0)
-    atomicMax(&prm->emax_bits[(blockIdx.x * (CF_BLOCK / 64) + (tid >> 6)) % EMAX_SLOTS],
+    atomicMax(&prm->emax_bits[(blockIdx.x * (CF_THREADS / 64) + (tid >> 6)) % EMAX_SLOTS],
               __float_as_uint(e32));
 }
 
 // Blocks of cull_fiber_kernel<Q, BATCH, TN> that the device holds at once
-// (register- or LDS-bound), queried once per process and kernel.
+// (register-bound), queried once per process and kernel.
 template <int Q, bool BATCH, bool TN>
 int64_t cf_grid() {
   static std::atomic<int64_t> g{0};
@@ -446,7 +574,7 @@ int64_t cf_grid() {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cull_fiber_kernel<Q, BATCH, TN>,
-                                                     CF_BLOCK, 0) != hipSuccess ||
+                                                     CF_THREADS, 0) != hipSuccess ||
         cus <= 0 || per <= 0)
       return 1024;
     v = (int64_t)cus * per;
@@ -590,7 +718,7 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
 }
 
 struct CullJob {
-  const uint4* pay;      // fiber payloads in input order [n][PAY_WORDS]
+  Payload pay;           // fiber payloads in input order
   const int32_t* perm;   // sorted position -> input index
   const PfParams* prm;   // frame (code scale)
   const uint8_t* cfeat;  // sorted columns [ncols_pad][16]
@@ -706,8 +834,10 @@ __device__ __forceinline__ bool quad_pair(const float* __restrict__ ar,
 // rows (see the top of this file).  With STATS the staged exact stage of the
 // other paths runs on the queued pairs instead (one lane per pair), to count
 // its tests; with MULTI accepted pairs go to the fibers' bundle slots.
+// (five waves per SIMD, 96 registers at most, where that needs no spills;
+// the block's LDS allows five blocks per compute unit)
 template <int Q, bool STATS, bool MULTI, bool BATCH>
-__global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, MultiOut mo,
+__global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS || MULTI ? 4 : 5))) void cull_kernel(CullJob job, Metric mt, MultiOut mo,
                                                        unsigned long long* __restrict__ counters) {
   using FT = typename Frag<Q>::T;
   constexpr int EB = QTraits<Q>::bytes;
@@ -734,7 +864,7 @@ __global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, M
   // together; positions past n are padding rows (zero codes, never pass,
   // empty box)
   FT afr[2];
-  uint4 w2s[2];
+  float2 cst[2];  // (-Ha, error bound)
   int32_t prow[2];
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
@@ -742,13 +872,25 @@ __global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, M
     const int32_t r = job.perm[p < n ? p : n - 1];
     prow[g] = r >= 0 && r < n ? r : 0;  // (always in range; the clamp only guards the reads)
   }
-  uint32_t sub[2] = {0u, 0u};
+  int32_t sub[2] = {0, 0}, loc[2] = {0, 0};
+  float len[2] = {0.0f, 0.0f};
+  const bool tn = (mt.flags & MF_TN) != 0;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    const uint4* P = job.pay + (int64_t)prow[g] * PAY_WORDS;
-    afr[g] = *(const FT*)((const uint8_t*)P + 8 * half * EB);
-    w2s[g] = P[2];
-    if (BATCH) sub[g] = P[3].x;
+    afr[g] = *(const FT*)(job.pay.codes + (int64_t)prow[g] * (16 * EB) + 8 * half * EB);
+    if (BATCH || job.pay.wide) {
+      const float4 r = ((const float4*)job.pay.rec)[prow[g]];
+      cst[g] = make_float2(r.x, r.y);
+      if (BATCH) {
+        sub[g] = __float_as_int(r.z);
+        loc[g] = __float_as_int(r.w);
+        if (tn) len[g] = job.pay.len[prow[g]];
+      } else {
+        len[g] = r.z;
+      }
+    } else {
+      cst[g] = ((const float2*)job.pay.rec)[prow[g]];
+    }
   }
   const float isf = (float)frame(job.prm, Q).is;  // a power of two
   // the union box of the wave's rows: each lane's 8 features of its two
@@ -763,13 +905,13 @@ __global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, M
   for (int g = 0; g < 2; ++g) {
     const bool valid = wbase + g * 32 + l31 < n;
     if (!valid) __builtin_memset(&afr[g], 0, sizeof(FT));
-    const float er = __uint_as_float(w2s[g].y);
+    const float er = cst[g].y;
     if (half == 0) {
       // a padding row's C operand is NaN: its products are NaN and never pass
-      s_nh[wave][g * 32 + l31] = valid ? __uint_as_float(w2s[g].x) : __builtin_nanf("");
-      s_idx[wave][g * 32 + l31] = valid ? (int32_t)w2s[g].z : 0;
-      s_len[wave][g * 32 + l31] = __uint_as_float(w2s[g].w);
-      if (BATCH) s_sub[wave][g * 32 + l31] = valid ? (int32_t)sub[g] : 0;
+      s_nh[wave][g * 32 + l31] = valid ? cst[g].x : __builtin_nanf("");
+      s_idx[wave][g * 32 + l31] = valid ? (BATCH ? loc[g] : prow[g]) : 0;
+      s_len[wave][g * 32 + l31] = len[g];
+      if (BATCH) s_sub[wave][g * 32 + l31] = valid ? sub[g] : 0;
     }
     uint8_t codes[sizeof(FT)];
     __builtin_memcpy(codes, &afr[g], sizeof(FT));
@@ -910,21 +1052,14 @@ __global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, M
     }
     return !(s > r2);
   };
-  // B: the MFMA bound on candidate tiles [0, nc), the next one's columns
-  // loading meanwhile; both groups (group 1 only when it holds a row)
+  // B: the MFMA bound on candidate tiles [0, nc), the columns of the next
+  // three loading meanwhile (a ring of three); both groups (group 1 only
+  // when it holds a row)
   auto products = [&](uint32_t nc) {
     wave_lds_sync();
     if (STATS && lane == 0)
       atomicAdd(counters + 5, (unsigned long long)nc * (g1 ? 2u : 1u));
-    FT bn;
-    float cbn = 0.0f;
-    uint32_t cnn = 0;
-    cload(0, bn, cbn, cnn);
-    for (uint32_t i = 0; i < nc; ++i) {
-      const FT b = bn;
-      const float cbv = cbn;
-      const uint32_t cent = cnn;
-      if (i + 1 < nc) cload(i + 1, bn, cbn, cnn);
+    auto step = [&](const FT& b, float cbv, uint32_t cent) {
       if (qn > (uint32_t)(CQ - CQ_ROOM)) {
         drain(qn);
         qn = 0;
@@ -940,6 +1075,24 @@ __global__ __launch_bounds__(64 * CW) void cull_kernel(CullJob job, Metric mt, M
         }
         const f32x16 a = Frag<Q>::mfma(afr[1], b, negh(1));
         if (wave_any(max16(a) >= cbv)) extract(a, 1, cent, cbv);
+      }
+    };
+    FT b0, b1, b2;
+    float cb0 = 0.0f, cb1 = 0.0f, cb2 = 0.0f;
+    uint32_t cn0 = 0, cn1 = 0, cn2 = 0;
+    cload(0, b0, cb0, cn0);
+    if (nc > 1) cload(1, b1, cb1, cn1);
+    if (nc > 2) cload(2, b2, cb2, cn2);
+    for (uint32_t i = 0; i < nc; i += 3) {
+      step(b0, cb0, cn0);
+      if (i + 3 < nc) cload(i + 3, b0, cb0, cn0);
+      if (i + 1 < nc) {
+        step(b1, cb1, cn1);
+        if (i + 4 < nc) cload(i + 4, b1, cb1, cn1);
+      }
+      if (i + 2 < nc) {
+        step(b2, cb2, cn2);
+        if (i + 5 < nc) cload(i + 5, b2, cb2, cn2);
       }
     }
     wave_lds_sync();  // the candidate list is rewritten after this
@@ -1052,7 +1205,7 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   const int64_t nk = std::max<int64_t>(std::max<int64_t>(n, m), 1);  // sort capacity
   // scratch: fiber payloads (input order), sort state (keys, the fiber
   // permutation), the centroid order, columns and tile boxes
-  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)n * PAY_WORDS * sizeof(uint4));
+  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)n * PAY_BYTES);
   rc = rc ? rc : grow_sort(pb, nk);
   rc = rc ? rc : grow(&pb.cperm, &pb.cperm_bytes, (size_t)std::max<int32_t>(m, 1) * 4);
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
@@ -1063,7 +1216,7 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   if (rc) return rc;
   if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
   PfParams* prm = (PfParams*)pb.emax;
-  uint4* pay = (uint4*)pb.fib_feat;
+  const Payload pay = payload_of(pb.fib_feat, n, (mt.flags & MF_TN) != 0);
   uint8_t* cfeat = (uint8_t*)pb.cen_feat;
   float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
   int32_t* ccent = (int32_t*)(cbias + ncols_pad);
@@ -1076,16 +1229,16 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   if (!cperm_cached && sort_centroids(cprep, m, prm, pb, nk, cperm, s)) return -1;
   // fibers: payloads and cells in input order, then the permutation
   {
-    const int64_t nb = (n + CF_BLOCK - 1) / CF_BLOCK;
+    const int64_t nb = (n + CF_FIB - 1) / CF_FIB;
     const FiberOut fo{pay, keys_a, mo ? nullptr : labels, mo ? nullptr : dists, nullptr, 0, 0,
                       nullptr, nullptr, 0};
     if (mt.flags & MF_TN) {
       const int64_t g = cf_grid<Q, false, true>();
-      cull_fiber_kernel<Q, false, true><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(
+      cull_fiber_kernel<Q, false, true><<<(unsigned)(nb < g ? nb : g), CF_THREADS, 0, s>>>(
           fibers, n, prm, fo);
     } else {
       const int64_t g = cf_grid<Q, false, false>();
-      cull_fiber_kernel<Q, false, false><<<(unsigned)(nb < g ? nb : g), CF_BLOCK, 0, s>>>(
+      cull_fiber_kernel<Q, false, false><<<(unsigned)(nb < g ? nb : g), CF_THREADS, 0, s>>>(
           fibers, n, prm, fo);
     }
   }
@@ -1137,7 +1290,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
       odst.push_back(dists[i * na + a]);
     }
     rows += nf[i];
-    blk += (nf[i] + CF_BLOCK - 1) / CF_BLOCK;
+    blk += (nf[i] + CF_FIB - 1) / CF_FIB;
   }
   if (rows == 0) return 0;
   if (rows >= ((int64_t)1 << 31)) return -4;  // sorted rows are indexed with 32 bits
@@ -1149,7 +1302,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   const int32_t super_max = (cpad_max + 255) / 256;
   const int64_t nk = std::max<int64_t>(rows, mmax);
   // scratch (allocated before any capture)
-  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)rows * PAY_WORDS * sizeof(uint4));
+  int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)rows * PAY_BYTES);
   rc = rc ? rc : grow_sort(pb, nk);
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
                       (size_t)cpad_max * (KPC * EB + 2 * sizeof(float)));
@@ -1185,7 +1338,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
     bb.citems_tab = bb.citems;
   }
   PfParams* prm = (PfParams*)pb.emax;
-  uint4* pay = (uint4*)pb.fib_feat;
+  const Payload pay = payload_of(pb.fib_feat, rows, true);
   uint8_t* cfeat = (uint8_t*)pb.cen_feat;
   uint32_t* keys_a = (uint32_t*)pb.keys;
   int32_t* vals_a = (int32_t*)pb.vals;
@@ -1199,9 +1352,9 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
     const FiberOut fo{pay, keys_a, nullptr, nullptr, dsubs, nsub, blk, dlab, ddst, na};
     const unsigned grid = (unsigned)(blk < g ? blk : g);
     if (tn)
-      cull_fiber_kernel<Q, true, true><<<grid, CF_BLOCK, 0, cs>>>(nullptr, 0, prm, fo);
+      cull_fiber_kernel<Q, true, true><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
     else
-      cull_fiber_kernel<Q, true, false><<<grid, CF_BLOCK, 0, cs>>>(nullptr, 0, prm, fo);
+      cull_fiber_kernel<Q, true, false><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
     if (radix_sort(rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs)) return -1;
     for (int32_t a = 0; a < na; ++a) {
       const int32_t m = at[a].m;
