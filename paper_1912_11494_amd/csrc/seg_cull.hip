@@ -269,31 +269,33 @@ __global__ __launch_bounds__(256) void cell_key_kernel(const float* __restrict__
 
 // Per-fiber payload in input (row) order, as arrays that the fiber kernel
 // writes whole (a partial memory line costs a read-modify-write) and the
-// culled kernel gathers a row at a time (two 64-byte sectors per row):
-//   codes  the 16 quantised feature codes, 16 x the code size
-//   rec    the row constants: (-Ha, error bound |Xq - X|), 8 bytes; with the
-//          length-normalised metric or in a batch (`wide`) 16 bytes,
-//          (-Ha, error bound, arc length, 0) or (-Ha, error bound, subject,
-//          index within the subject)
-//   len    the arc length of a batch row (length-normalised metric)
+// culled kernel gathers a row at a time:
+//   codes  the quantised feature codes, 16 x the code size.  Feature 15 of
+//          the symmetric map is zero; with 2-byte codes its slot holds the
+//          row's error bound |Xq - X| instead, as an fp16 value rounded up
+//          (+inf for a row that bypasses the cut), so a row is one 32-byte
+//          read and the culled kernel derives -Ha from the codes itself
+//   cst    (-Ha, error bound) for 1-byte codes
+//   ext    (arc length, subject, index within the subject, 0) with the
+//          length-normalised metric or in a batch (`ext_on`)
 // A fiber with a non-finite coordinate gets -Ha = +inf (it bypasses the cut),
 // error bound +inf (its box is unbounded) and zero codes.  The arc length is
 // that of arc_length.
 struct Payload {
   uint8_t* codes;
-  void* rec;
-  float* len;
-  int wide;
+  float2* cst;
+  float4* ext;
+  int ext_on;
 };
-constexpr size_t PAY_BYTES = 32 + 16 + 4;  // per row, the largest layout
+constexpr size_t PAY_BYTES = 32 + 8 + 16;  // per row, the largest layout
 
 // The payload arrays carved from one allocation of rows * PAY_BYTES.
-inline Payload payload_of(void* base, int64_t rows, bool wide) {
+inline Payload payload_of(void* base, int64_t rows, bool ext_on) {
   Payload p;
   p.codes = (uint8_t*)base;
-  p.rec = p.codes + (size_t)rows * 32;
-  p.len = (float*)((uint8_t*)p.rec + (size_t)rows * 16);
-  p.wide = wide ? 1 : 0;
+  p.cst = (float2*)(p.codes + (size_t)rows * 32);
+  p.ext = (float4*)(p.cst + rows);
+  p.ext_on = ext_on ? 1 : 0;
   return p;
 }
 
@@ -490,13 +492,6 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
     uint32_t o0 = sl == 0 ? c[0] : c[1], o1 = sl == 0 ? c[1] : c[2];
     uint32_t o2 = sl == 0 ? c[2] : c[3], o3 = sl == 3 ? 0u : nxt;
     if (!finite) o0 = o1 = o2 = o3 = 0u;  // a bypassing row: zero codes
-    const int64_t f = bs.row + fb;     // payload row
-    const int64_t loc = bs.local + fb;  // index within the subject
-    uint8_t* C = fo.pay.codes + f * (16 * EB);
-    if (EB == 2)
-      *(uint2*)(C + 8 * sl) = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
-    else
-      *(uint32_t*)(C + 4 * sl) = o0 | (o1 << 8) | (o2 << 16) | (o3 << 24);
     float nh, er;
     if (!finite) {
       nh = __builtin_inff();
@@ -510,6 +505,15 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
       er = __double2float_ru(e);
       e32 = fmaxf(e32, er);
     }
+    // 2-byte codes: the error bound in the slot of feature 15
+    if (EB == 2 && sl == 3) o3 = (uint32_t)__half_as_ushort(__float2half_ru(er));
+    const int64_t f = bs.row + fb;     // payload row
+    const int64_t loc = bs.local + fb;  // index within the subject
+    uint8_t* C = fo.pay.codes + f * (16 * EB);
+    if (EB == 2)
+      *(uint2*)(C + 8 * sl) = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
+    else
+      *(uint32_t*)(C + 4 * sl) = o0 | (o1 << 8) | (o2 << 16) | (o3 << 24);
     if (sl == 0) {
       uint32_t code = 0;
       const float a3[3] = {A.x, A.y, A.z};
@@ -537,15 +541,10 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
         r[62] = rec[62];
         len = arc_length(r);
       }
-      if (BATCH) {
-        ((float4*)fo.pay.rec)[f] = make_float4(nh, er, __int_as_float(bs.sub),
-                                               __int_as_float((int32_t)loc));
-        if (TN) fo.pay.len[f] = len;
-      } else if (TN) {
-        ((float4*)fo.pay.rec)[f] = make_float4(nh, er, len, 0.0f);
-      } else {
-        ((float2*)fo.pay.rec)[f] = make_float2(nh, er);
-      }
+      if (EB == 1) fo.pay.cst[f] = make_float2(nh, er);
+      if (BATCH || TN)
+        fo.pay.ext[f] = make_float4(len, __int_as_float(BATCH ? bs.sub : 0),
+                                    __int_as_float(BATCH ? (int32_t)loc : 0), 0.0f);
     }
     if (BATCH) {
       if (sl == 1)
@@ -583,54 +582,118 @@ int64_t cf_grid() {
   return v;
 }
 
-// Order-preserving integer image of a float (its own inverse), so minima and
-// maxima can go through integer lane permutations.
-__device__ __forceinline__ int fkey(float f) {
-  const int i = __float_as_int(f);
-  return i ^ ((i >> 31) & 0x7fffffff);
+// Order the wave's LDS writes before its later LDS reads (lanes read what
+// other lanes of the same wave wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-__device__ __forceinline__ float fkey_inv(int i) { return __int_as_float(i ^ ((i >> 31) & 0x7fffffff)); }
 
-// One DPP step of eight minima and eight maxima (lane permutation CTRL).
-template <int CTRL>
-__device__ __forceinline__ void dpp_minmax8(int* xl, int* xh) {
+// Codes as order-preserving unsigned 16-bit values, two per word: 2-byte
+// codes (fp16, bf16: sign and magnitude) map h to h | 0x8000 when positive
+// and to ~h when negative; 1-byte codes (e4m3, one per 16-bit lane) the same
+// within their low byte.
+template <int EB>
+__device__ __forceinline__ uint32_t ord_codes(uint32_t w) {
+  if (EB == 2) {
+    const uint32_t neg = (w >> 15) & 0x00010001u;
+    return w ^ ((neg * 0xFFFFu) | 0x80008000u);
+  } else {
+    const uint32_t neg = (w >> 7) & 0x00010001u;
+    return w ^ ((neg * 0xFFu) | 0x00800080u);
+  }
+}
+template <int EB>
+__device__ __forceinline__ uint32_t unord_code(uint32_t o) {
+  if (EB == 2) return (o & 0x8000u) ? (o ^ 0x8000u) : (~o & 0xFFFFu);
+  return (o & 0x80u) ? (o ^ 0x80u) : (~o & 0xFFu);
+}
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b) {
+  u16x2 x, y;
+  __builtin_memcpy(&x, &a, 4);
+  __builtin_memcpy(&y, &b, 4);
+  const u16x2 r = __builtin_elementwise_min(x, y);
+  uint32_t o;
+  __builtin_memcpy(&o, &r, 4);
+  return o;
+}
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
+  u16x2 x, y;
+  __builtin_memcpy(&x, &a, 4);
+  __builtin_memcpy(&y, &b, 4);
+  const u16x2 r = __builtin_elementwise_max(x, y);
+  uint32_t o;
+  __builtin_memcpy(&o, &r, 4);
+  return o;
+}
+
+// One DPP step of the packed minima and maxima (lane permutation CTRL; rows
+// whose bit is clear in RMASK keep their values).
+template <int CTRL, int RMASK>
+__device__ __forceinline__ void dpp_pk_minmax(uint32_t* m, uint32_t* M) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int a = __builtin_amdgcn_mov_dpp(xl[k], CTRL, 0xF, 0xF, false);
-    const int b = __builtin_amdgcn_mov_dpp(xh[k], CTRL, 0xF, 0xF, false);
-    xl[k] = a < xl[k] ? a : xl[k];
-    xh[k] = b > xh[k] ? b : xh[k];
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_update_dpp((int)m[j], (int)m[j], CTRL, RMASK, 0xF, false);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_update_dpp((int)M[j], (int)M[j], CTRL, RMASK, 0xF, false);
+    m[j] = pk_min_u16(m[j], a);
+    M[j] = pk_max_u16(M[j], b);
   }
 }
 
-// Lowest of lo[k] and highest of hi[k] over each half wave, k < 8, as
-// wave-uniform values: lanes 0-31 give ulo[k] / uhi[k], lanes 32-63 give
-// ulo[8 + k] / uhi[8 + k].  Within each row of 16 lanes by two quad
-// permutations and rotations by 4 and 8 (all sixteen values step by step, so
-// consecutive instructions do not depend on each other), then the two rows
-// of each half through lanes 15 and 31, 47 and 63.
-__device__ __forceinline__ void half_wave_box8(const float* lo, const float* hi, float* ulo,
-                                               float* uhi) {
-  int xl[8], xh[8];
+// The wave's union box from each lane's packed code minima / maxima (half 0:
+// features 0-7, half 1: 8-15) and error bound: minima and maxima over each
+// half wave (within rows of 16 lanes, then row 0 into 1 and row 2 into 3),
+// the results of lanes 31 and 63 through LDS to lane f (lowest) and 16 + f
+// (highest) of feature f, decoded and widened there by the largest error
+// bound and a relative 2^-23 (one rounding each), then read out as
+// wave-uniform values.  A non-finite error bound leaves the box unbounded.
+template <int Q>
+__device__ __forceinline__ void union_box(uint32_t* m, uint32_t* M, float emax, float isf,
+                                          uint32_t* s_b, float* ulo, float* uhi) {
+  constexpr int EB = QTraits<Q>::bytes;
+  dpp_pk_minmax<0xB1, 0xF>(m, M);   // quad_perm [1,0,3,2]
+  dpp_pk_minmax<0x4E, 0xF>(m, M);   // quad_perm [2,3,0,1]
+  dpp_pk_minmax<0x124, 0xF>(m, M);  // row_ror:4
+  dpp_pk_minmax<0x128, 0xF>(m, M);  // row_ror:8
+  dpp_pk_minmax<0x142, 0xA>(m, M);  // row_bcast:15 into rows 1 and 3
+  // the largest error bound (non-negative: its bits order as integers)
+  int e = __float_as_int(emax);
+  e = max(e, __builtin_amdgcn_update_dpp(e, e, 0xB1, 0xF, 0xF, false));
+  e = max(e, __builtin_amdgcn_update_dpp(e, e, 0x4E, 0xF, 0xF, false));
+  e = max(e, __builtin_amdgcn_update_dpp(e, e, 0x124, 0xF, 0xF, false));
+  e = max(e, __builtin_amdgcn_update_dpp(e, e, 0x128, 0xF, 0xF, false));
+  const int e0 = max(__builtin_amdgcn_readlane(e, 15), __builtin_amdgcn_readlane(e, 31));
+  const int e1 = max(__builtin_amdgcn_readlane(e, 47), __builtin_amdgcn_readlane(e, 63));
+  const float er = __int_as_float(max(e0, e1));
+  const int lane = (int)lane_id();
+  if ((lane & 31) == 31) {
+    const int h = lane >> 5;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    xl[k] = fkey(lo[k]);
-    xh[k] = fkey(hi[k]);
+    for (int j = 0; j < 4; ++j) {
+      s_b[4 * h + j] = m[j];      // 16-bit values of features 8h + 2j, 8h + 2j + 1
+      s_b[8 + 4 * h + j] = M[j];
+    }
   }
-  dpp_minmax8<0xB1>(xl, xh);   // quad_perm [1,0,3,2]
-  dpp_minmax8<0x4E>(xl, xh);   // quad_perm [2,3,0,1]
-  dpp_minmax8<0x124>(xl, xh);  // row_ror:4
-  dpp_minmax8<0x128>(xl, xh);  // row_ror:8
+  wave_lds_sync();
+  const uint32_t o = ((const unsigned short*)s_b)[lane & 31];
+  const float x = QTraits<Q>::decf(unord_code<EB>(o)) * isf;  // exact
+  float v;
+  if ((lane & 31) < 16) {
+    const float l = x - er;
+    v = l - fabsf(l) * 0x1p-23f - 0x1p-126f;
+    if (!(er < __builtin_inff())) v = -__builtin_inff();
+  } else {
+    const float h = x + er;
+    v = h + fabsf(h) * 0x1p-23f + 0x1p-126f;
+    if (!(er < __builtin_inff())) v = __builtin_inff();
+  }
+  const int vi = __float_as_int(v);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int l0 = __builtin_amdgcn_readlane(xl[k], 15), l1 = __builtin_amdgcn_readlane(xl[k], 31);
-    const int l2 = __builtin_amdgcn_readlane(xl[k], 47), l3 = __builtin_amdgcn_readlane(xl[k], 63);
-    const int h0 = __builtin_amdgcn_readlane(xh[k], 15), h1 = __builtin_amdgcn_readlane(xh[k], 31);
-    const int h2 = __builtin_amdgcn_readlane(xh[k], 47), h3 = __builtin_amdgcn_readlane(xh[k], 63);
-    ulo[k] = fkey_inv(l0 < l1 ? l0 : l1);
-    ulo[8 + k] = fkey_inv(l2 < l3 ? l2 : l3);
-    uhi[k] = fkey_inv(h0 > h1 ? h0 : h1);
-    uhi[8 + k] = fkey_inv(h2 > h3 ? h2 : h3);
+  for (int k = 0; k < BOXD; ++k) {
+    ulo[k] = __int_as_float(__builtin_amdgcn_readlane(vi, k));
+    uhi[k] = __int_as_float(__builtin_amdgcn_readlane(vi, 16 + k));
   }
 }
 
@@ -746,14 +809,6 @@ constexpr int CROUND = 256;    // centroid tiles per candidate round
 constexpr int CQ = 1280;       // survivor queue entries per wave
 constexpr int CQ_ROOM = 1024;  // the most entries one (tile, group) product adds
 
-// Order the wave's LDS writes before its later LDS reads (lanes read what
-// other lanes of the same wave wrote).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Nine consecutive floats (three points) from a 4-byte aligned address.
 __device__ __forceinline__ void load9(const float* __restrict__ p, float* v) {
   const f4u a = *(const f4u*)p;
@@ -849,6 +904,7 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   __shared__ uint32_t s_cand[CW][CROUND];                      // passing tiles
   __shared__ uint32_t s_q[CW][CQ];                             // centroid << 6 | row
   __shared__ unsigned long long s_best[CW][64];                // argmin key of each row
+  __shared__ uint32_t s_box[CW][16];                           // union box (16-bit codes)
   const int lane = (int)(threadIdx.x & 63);
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int half = lane >> 5;
@@ -861,10 +917,8 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   StageCounts sc{counters};
 
   // both groups' permutation entries, then both groups' payloads, in flight
-  // together; positions past n are padding rows (zero codes, never pass,
-  // empty box)
+  // together; positions past n are padding rows (never pass, no box)
   FT afr[2];
-  float2 cst[2];  // (-Ha, error bound)
   int32_t prow[2];
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
@@ -872,75 +926,81 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
     const int32_t r = job.perm[p < n ? p : n - 1];
     prow[g] = r >= 0 && r < n ? r : 0;  // (always in range; the clamp only guards the reads)
   }
-  int32_t sub[2] = {0, 0}, loc[2] = {0, 0};
-  float len[2] = {0.0f, 0.0f};
-  const bool tn = (mt.flags & MF_TN) != 0;
+  float2 cst[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};  // 1-byte codes
+  float4 ext[2] = {make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float4(0.0f, 0.0f, 0.0f, 0.0f)};
+  const bool with_ext = BATCH || job.pay.ext_on;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     afr[g] = *(const FT*)(job.pay.codes + (int64_t)prow[g] * (16 * EB) + 8 * half * EB);
-    if (BATCH || job.pay.wide) {
-      const float4 r = ((const float4*)job.pay.rec)[prow[g]];
-      cst[g] = make_float2(r.x, r.y);
-      if (BATCH) {
-        sub[g] = __float_as_int(r.z);
-        loc[g] = __float_as_int(r.w);
-        if (tn) len[g] = job.pay.len[prow[g]];
-      } else {
-        len[g] = r.z;
-      }
-    } else {
-      cst[g] = ((const float2*)job.pay.rec)[prow[g]];
-    }
+    if (EB == 1) cst[g] = job.pay.cst[prow[g]];
+    if (with_ext) ext[g] = job.pay.ext[prow[g]];
   }
-  const float isf = (float)frame(job.prm, Q).is;  // a power of two
-  // the union box of the wave's rows: each lane's 8 features of its two
-  // rows, widened by the rows' error bounds, reduced over the half wave
-  float lo[8], hi[8];
+  const Frame fr = frame(job.prm, Q);
+  const float isf = (float)fr.is;  // a power of two
+  const double gam = gamma_acc(KPC);
+  // per row: the error bound and -Ha (from the codes, as the fiber kernel
+  // computes it, with 2-byte codes); the wave's largest error bound; the
+  // codes as order-preserving 16-bit values, lowest and highest over the
+  // wave's valid rows (padding rows take the neutral values)
+  float emax = 0.0f;
+  uint32_t omin[4], omax[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    lo[k] = __builtin_inff();
-    hi[k] = -__builtin_inff();
+  for (int j = 0; j < 4; ++j) {
+    omin[j] = 0xFFFFFFFFu;
+    omax[j] = 0u;
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const bool valid = wbase + g * 32 + l31 < n;
-    if (!valid) __builtin_memset(&afr[g], 0, sizeof(FT));
-    const float er = cst[g].y;
+    uint32_t w[4];
+    float er, nh;
+    if (EB == 2) {
+      __builtin_memcpy(w, &afr[g], 16);
+      // half 1 holds features 8-15: the slot of 15 is the error bound
+      const float eh = half ? __half2float(__ushort_as_half((unsigned short)(w[3] >> 16))) : 0.0f;
+      if (half) w[3] &= 0xFFFFu;
+      __builtin_memcpy(&afr[g], w, 16);
+      er = fmaxf(eh, __shfl_xor(eh, 32));
+      double nqp = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double x = (double)(QTraits<Q>::decf((w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) * isf);
+        nqp += x * x;
+      }
+      const double nq = nqp + __shfl_xor(nqp, 32);  // the same in both halves
+      const double ha = (0.5 - gam) * nq * (1.0 - 0x1p-40);  // round towards passing
+      nh = er < __builtin_inff() ? __double2float_ru(-ha * fr.s2) : __builtin_inff();
+    } else {
+      er = cst[g].y;
+      nh = cst[g].x;
+      // eight 1-byte codes as 16-bit lanes
+      uint64_t b8;
+      __builtin_memcpy(&b8, &afr[g], 8);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        w[j] = (uint32_t)((b8 >> (16 * j)) & 0xFFu) | ((uint32_t)((b8 >> (16 * j + 8)) & 0xFFu) << 16);
+    }
     if (half == 0) {
       // a padding row's C operand is NaN: its products are NaN and never pass
-      s_nh[wave][g * 32 + l31] = valid ? cst[g].x : __builtin_nanf("");
-      s_idx[wave][g * 32 + l31] = valid ? (BATCH ? loc[g] : prow[g]) : 0;
-      s_len[wave][g * 32 + l31] = len[g];
-      if (BATCH) s_sub[wave][g * 32 + l31] = valid ? sub[g] : 0;
+      s_nh[wave][g * 32 + l31] = valid ? nh : __builtin_nanf("");
+      s_idx[wave][g * 32 + l31] = valid ? (BATCH ? __float_as_int(ext[g].z) : prow[g]) : 0;
+      s_len[wave][g * 32 + l31] = ext[g].x;
+      if (BATCH) s_sub[wave][g * 32 + l31] = valid ? __float_as_int(ext[g].y) : 0;
     }
-    uint8_t codes[sizeof(FT)];
-    __builtin_memcpy(codes, &afr[g], sizeof(FT));
+    if (valid) {
+      emax = fmaxf(emax, er);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      uint32_t b;
-      if (EB == 2)
-        b = (uint32_t)codes[2 * k] | ((uint32_t)codes[2 * k + 1] << 8);
-      else
-        b = codes[k];
-      const float xq = QTraits<Q>::decf(b) * isf;  // exact (a power-of-two scale)
-      const float l = xq - er, h = xq + er;
-      // one rounding each: widen by a relative 2^-23 (and a tiny absolute)
-      float rl = l - fabsf(l) * 0x1p-23f - 0x1p-126f;
-      float rh = h + fabsf(h) * 0x1p-23f + 0x1p-126f;
-      if (!(er < __builtin_inff())) {  // a non-finite row: unbounded
-        rl = -__builtin_inff();
-        rh = __builtin_inff();
-      }
-      if (valid) {
-        lo[k] = fminf(lo[k], rl);
-        hi[k] = fmaxf(hi[k], rh);
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t o = ord_codes<EB>(w[j]);
+        omin[j] = pk_min_u16(omin[j], o);
+        omax[j] = pk_max_u16(omax[j], o);
       }
     }
   }
   // wave-uniform (scalar) union box: features 0-7 from half 0, 8-15 from
-  // half 1
+  // half 1, widened by the largest error bound
   float ulo[BOXD], uhi[BOXD];
-  half_wave_box8(lo, hi, ulo, uhi);
+  union_box<Q>(omin, omax, emax, isf, s_box[wave], ulo, uhi);
   s_best[wave][lane] = NO_KEY;
   wave_lds_sync();
 
