@@ -286,8 +286,9 @@ def batch_inputs(workers):
 def bench_batch(args, atl, subs, P, hip):
     """The batch workload: 16 subjects (0.3M-4.1M fibers) against two atlases
     (3,600 and 10,000 centroids), one label per (fiber, atlas).  Times the
-    batch entry point on its default route (fp16, tile-culled: every subject's
-    fibers sorted together, one culled pass per atlas, in a cached HIP graph),
+    batch entry point on its default route (fp16, tile-culled: subjects in
+    chunks of at most 2^22 fibers, each chunk's payloads computed once and
+    sorted together, then one culled pass per atlas, all in a cached HIP graph),
     its graph-captured flattened launches (bf16 streaming, plain), and one
     call per (subject, atlas) pair, plain and tile-culled; every route's
     labels and distances are compared with the sequential plain calls."""

@@ -208,9 +208,11 @@ int seg_segment_atlas(const seg_atlas* atlas, const float* fibers, int64_t n_fib
 /*
  * Segment n_subjects subjects against n_atlases prepared atlases in one call.
  * SEG_PREFILTER_BF16 / FP16 / FP8 at tile 0 (or 8) run the sorted,
- * tile-culled form on the whole batch: the fibers of every subject get their
- * features once (one quantisation frame over all the atlases) and are sorted
- * together by space, then each atlas takes one culled pass over all of them.
+ * tile-culled form on the batch in chunks of consecutive subjects of at most
+ * 2^22 fibers (a larger subject is a chunk of its own): the fibers of a chunk
+ * get their features once (one quantisation frame over all the atlases) and
+ * are sorted together by space, then each atlas takes one culled pass over
+ * the chunk.
  * SEG_PLAIN, SEG_PREFILTER_BF16_ORIENTED and the streaming tiles of the
  * symmetric prefilters run one launch of the fused kernel over a flattened
  * list of (subject, atlas, fiber block) work items, costliest atlas first.

@@ -1325,32 +1325,47 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// A batch of subjects against prepared atlases: the payloads, cells and
-// cells of every subject's fibers in one launch (one frame over the union of
-// the atlas boxes), one sort of all rows together (fibers of every subject
-// share the cells), then per atlas its columns and one culled pass over all
-// rows, each row writing its subject's output for that atlas.  The launches
+// A batch of subjects against prepared atlases, in chunks of consecutive
+// subjects of at most CHUNK_ROWS fibers (a subject with more is a chunk of
+// its own), so that a chunk's payloads stay in the memory-side cache for the
+// gathers of the culled passes: per chunk the payloads and cells of its
+// fibers in one launch (one frame over the union of the atlas boxes, set up
+// once), one sort of its rows, then per atlas the columns (their constants
+// cover the largest fiber error seen so far) and one culled pass over the
+// chunk, each row writing its subject's output for that atlas.  The launches
 // are captured once per launch shape into a HIP graph and replayed.
+constexpr int64_t CHUNK_ROWS = (int64_t)1 << 22;
 template <int Q>
 int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cperms,
                       const float* const* fibers, const int64_t* nf, int32_t ns,
                       int32_t* const* labels, float* const* dists, int mflags, PrefilterBuf& pb,
                       BatchBuf& bb, hipStream_t s) {
   constexpr int EB = QTraits<Q>::bytes;
-  // subjects with fibers, in order, and their outputs
+  // subjects with fibers, in order, and their outputs; chunks of them, each
+  // subject's first row and payload batch counted within its chunk
+  struct Chunk {
+    int32_t sub0, nsub;
+    int64_t rows, blk;
+  };
   std::vector<SubDev> subs;
+  std::vector<Chunk> chunks;
   std::vector<int32_t*> olab;
   std::vector<float*> odst;
-  int64_t rows = 0, blk = 0;
+  int64_t rows = 0;  // the largest chunk
   for (int32_t i = 0; i < ns; ++i) {
     if (nf[i] <= 0) continue;
-    subs.push_back(SubDev{fibers[i], nf[i], rows, blk});
+    if (chunks.empty() || (chunks.back().rows > 0 && chunks.back().rows + nf[i] > CHUNK_ROWS))
+      chunks.push_back(Chunk{(int32_t)subs.size(), 0, 0, 0});
+    Chunk& ch = chunks.back();
+    subs.push_back(SubDev{fibers[i], nf[i], ch.rows, ch.blk});
     for (int32_t a = 0; a < na; ++a) {
       olab.push_back(labels[i * na + a]);
       odst.push_back(dists[i * na + a]);
     }
-    rows += nf[i];
-    blk += (nf[i] + CF_FIB - 1) / CF_FIB;
+    ++ch.nsub;
+    ch.rows += nf[i];
+    ch.blk += (nf[i] + CF_FIB - 1) / CF_FIB;
+    rows = std::max(rows, ch.rows);
   }
   if (rows == 0) return 0;
   if (rows >= ((int64_t)1 << 31)) return -4;  // sorted rows are indexed with 32 bits
@@ -1409,31 +1424,37 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   auto enqueue = [&](hipStream_t cs) -> int {
     launch_pf_init(prm, cs);
     for (int32_t a = 0; a < na; ++a) launch_pf_bbox_acc(prm, at[a].cprep, at[a].m, cs);
-    const FiberOut fo{pay, keys_a, nullptr, nullptr, dsubs, nsub, blk, dlab, ddst, na};
-    const unsigned grid = (unsigned)(blk < g ? blk : g);
-    if (tn)
-      cull_fiber_kernel<Q, true, true><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
-    else
-      cull_fiber_kernel<Q, true, false><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
-    if (radix_sort(rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs)) return -1;
-    for (int32_t a = 0; a < na; ++a) {
-      const int32_t m = at[a].m;
-      if (m <= 0) continue;  // every output already holds (-1, +inf)
-      const int32_t ncols_pad = (m + 31) / 32 * 32;
-      const int32_t ntiles = ncols_pad / 32;
-      const int32_t nsuper = (ncols_pad + 255) / 256;
-      float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
-      int32_t* ccent = (int32_t*)(cbias + ncols_pad);
-      float* sbox = tbox + (size_t)TROWS * ntiles;
-      cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(at[a].cprep, m, ncols_pad, cperms[a],
-                                                             prm, cfeat, cbias, ccent, tbox, sbox);
-      const CullJob job{pay,   perm,  prm,     cfeat, cbias, ccent, tbox, sbox, ntiles,
-                        nsuper, nullptr, rows, at[a].cprep, at[a].bid, nullptr, nullptr, dsubs,
-                        dlab,  ddst,  na,      a};
-      const MultiOut mout{nullptr, 0, nullptr, nullptr};
-      cull_kernel<Q, false, false, true>
-          <<<(unsigned)((rows + 64 * CW - 1) / (64 * CW)), 64 * CW, 0, cs>>>(
-              job, Metric{at[a].cext, mflags}, mout, nullptr);
+    for (const Chunk& ch : chunks) {
+      SubDev* csubs = dsubs + ch.sub0;
+      int32_t* const* clab = dlab + (size_t)ch.sub0 * na;
+      float* const* cdst = ddst + (size_t)ch.sub0 * na;
+      const FiberOut fo{pay, keys_a, nullptr, nullptr, csubs, ch.nsub, ch.blk, clab, cdst, na};
+      const unsigned grid = (unsigned)(ch.blk < g ? ch.blk : g);
+      if (tn)
+        cull_fiber_kernel<Q, true, true><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
+      else
+        cull_fiber_kernel<Q, true, false><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
+      if (radix_sort(ch.rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs))
+        return -1;
+      for (int32_t a = 0; a < na; ++a) {
+        const int32_t m = at[a].m;
+        if (m <= 0) continue;  // every output already holds (-1, +inf)
+        const int32_t ncols_pad = (m + 31) / 32 * 32;
+        const int32_t ntiles = ncols_pad / 32;
+        const int32_t nsuper = (ncols_pad + 255) / 256;
+        float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
+        int32_t* ccent = (int32_t*)(cbias + ncols_pad);
+        float* sbox = tbox + (size_t)TROWS * ntiles;
+        cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(
+            at[a].cprep, m, ncols_pad, cperms[a], prm, cfeat, cbias, ccent, tbox, sbox);
+        const CullJob job{pay,    perm,    prm,      cfeat,      cbias, ccent,  tbox,
+                          sbox,   ntiles,  nsuper,   nullptr,    ch.rows, at[a].cprep,
+                          at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a};
+        const MultiOut mout{nullptr, 0, nullptr, nullptr};
+        cull_kernel<Q, false, false, true>
+            <<<(unsigned)((ch.rows + 64 * CW - 1) / (64 * CW)), 64 * CW, 0, cs>>>(
+                job, Metric{at[a].cext, mflags}, mout, nullptr);
+      }
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
   };

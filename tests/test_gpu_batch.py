@@ -258,3 +258,36 @@ def test_batch_full_size_sampled(seg):
                 assert np.array_equal(lab, want[i][a][0]), (mode, i, a)
                 assert np.array_equal(dist, want[i][a][1]), (mode, i, a)
         del outs
+
+
+@pytest.mark.workloads("batch-16-subjects-x-2-atlases")
+def test_batch_culled_chunks_match_single_calls(seg):
+    """The tile-culled batch splits its subjects into chunks of at most 2^22
+    fibers (consecutive subjects; payloads of a chunk stay cached for its
+    passes).  Subjects of 2.32M, 1.0M, 0.9M and 2.0M fibers make two chunks of
+    two subjects each; every (subject, atlas) output equals the one-subject
+    call, itself checked against the oracle elsewhere."""
+    import torch
+
+    wl = "batch-16-subjects-x-2-atlases"
+    atl = synth.workload_atlases(wl)
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    f0 = torch.from_numpy(inputs.fibers(wl, 0)).to(d)
+    f1 = torch.from_numpy(inputs.fibers(wl, 1)).to(d)
+    gf = [f0, f1[:1_000_000], f1[1_000_000:1_900_000], f0[:2_000_000]]
+    gf = [g.contiguous() for g in gf]
+    log(f"batch chunks: subjects {[int(g.shape[0]) for g in gf]}")
+    for mode in ("fp16", "fp8"):
+        outs = seg.segment_batch(ga, gf, mode=mode, tile=0)
+        torch.cuda.synchronize()
+        for i, f in enumerate(gf):
+            for a, at in enumerate(atl):
+                c = torch.from_numpy(at.centroids).to(d)
+                b = torch.from_numpy(at.bundle_id).to(d)
+                t = torch.from_numpy(at.thresholds).to(d)
+                lab, dist = seg.segment(f, c, b, t, mode=mode)
+                torch.cuda.synchronize()
+                assert torch.equal(outs[i][a][0], lab), (mode, i, a)
+                assert torch.equal(outs[i][a][1], dist), (mode, i, a)
+        del outs
