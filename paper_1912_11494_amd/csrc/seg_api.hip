@@ -889,7 +889,7 @@ int64_t seg_scratch_bytes(void* stream) {
   t += sc.atlas.cap * (int64_t)(seg::CREC_BYTES + sizeof(float4) + 2 * sizeof(int32_t) +
                                 2 * sizeof(float));
   t += (int64_t)(p.fib_feat_bytes + p.cen_feat_bytes + p.fib_h_bytes + p.tbox_bytes +
-                 p.keys_bytes + p.vals_bytes + p.hist_bytes + p.cperm_bytes);
+                 p.keys_bytes + p.vals_bytes + p.hist_bytes + p.cperm_bytes + p.rank_bytes);
   if (p.emax) t += (int64_t)seg::pf_params_bytes();
   t += (int64_t)(b.items_bytes + b.fib_feat_bytes + b.fib_h_bytes + b.cen_feat_bytes +
                  b.citems_bytes);

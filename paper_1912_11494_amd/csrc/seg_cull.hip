@@ -112,31 +112,44 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __r
   s_cnt[tid] = 0u;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_IPB;
+  uint32_t kr[RS_IPB / RS_THREADS];
+#pragma unroll
   for (int j = 0; j < RS_IPB / RS_THREADS; ++j) {
     const int64_t i = base + (int64_t)j * RS_THREADS + tid;
-    if (i < n) atomicAdd(&s_cnt[digit_of(keys[i], shift)], 1u);
+    kr[j] = i < n ? keys[i] : 0u;
   }
+#pragma unroll
+  for (int j = 0; j < RS_IPB / RS_THREADS; ++j)
+    if (base + (int64_t)j * RS_THREADS + tid < n) atomicAdd(&s_cnt[digit_of(kr[j], shift)], 1u);
   __syncthreads();
   hist[(int64_t)tid * nblocks + blockIdx.x] = s_cnt[tid];
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns
-// the exclusive prefix and the total in *tot.
+// the exclusive prefix and the total in *tot.  Each wave scans its 64 values
+// with lane shuffles, then one exchange of the four wave totals through LDS.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
                                                           uint32_t* tot) {
   const int tid = (int)threadIdx.x;
-  s_tmp[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < RS_THREADS; off <<= 1) {
-    const uint32_t x = tid >= off ? s_tmp[tid - off] : 0u;
-    __syncthreads();
-    s_tmp[tid] += x;
-    __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
-  const uint32_t incl = s_tmp[tid];
-  *tot = s_tmp[RS_THREADS - 1];
+  if (lane == 63) s_tmp[w] = x;
   __syncthreads();
-  return incl - v;
+  uint32_t pre = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < RS_THREADS / 64; ++k) {
+    const uint32_t t = s_tmp[k];
+    pre += k < w ? t : 0u;
+    all += t;
+  }
+  *tot = all;
+  __syncthreads();  // s_tmp may be rewritten after this
+  return pre + x - v;
 }
 
 // One block per digit: exclusive scan of hist[digit][*] in place; the
@@ -196,12 +209,24 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
   const int lane = tid & 63;
   const int wave = tid >> 6;
   for (int w = 0; w < WAVES; ++w) s_cnt[w][tid] = 0u;
-  __syncthreads();
   const int64_t bstart = (int64_t)blockIdx.x * RS_IPB;
   const int64_t wb = bstart + (int64_t)wave * RS_IPW;
+  // the wave's keys and values, all loads in flight at once (the ranking
+  // below depends on LDS state round by round, so loads issued there would
+  // each wait a full memory latency)
+  uint32_t kr[RS_ROUNDS];
+  int32_t vr[RS_ROUNDS];
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = wb + r * 64 + lane;
-    if (i < n) atomicAdd(&s_cnt[wave][digit_of(keys_in[i], shift)], 1u);
+    kr[r] = i < n ? keys_in[i] : 0u;
+    vr[r] = i < n ? (vals_in ? vals_in[i] : (int32_t)i) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = wb + r * 64 + lane;
+    if (i < n) atomicAdd(&s_cnt[wave][digit_of(kr[r], shift)], 1u);
   }
   __syncthreads();
   {
@@ -224,10 +249,11 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
   }
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = wb + r * 64 + lane;
     const bool valid = i < n;
-    const uint32_t key = valid ? keys_in[i] : 0u;
+    const uint32_t key = kr[r];
     const uint32_t d = digit_of(key, shift);
     uint64_t mask = __ballot(valid);
 #pragma unroll
@@ -243,7 +269,7 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     __builtin_amdgcn_wave_barrier();
     if (valid) {
       s_key[start + rank] = key;
-      s_val[start + rank] = vals_in ? vals_in[i] : (int32_t)i;
+      s_val[start + rank] = vr[r];
     }
   }
   __syncthreads();
@@ -299,6 +325,14 @@ inline Payload payload_of(void* base, int64_t rows, bool ext_on) {
   return p;
 }
 
+// Order the wave's LDS writes before its later LDS reads (lanes read what
+// other lanes of the same wave wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Four lanes per fiber (a quad); a block takes batches of CF_FIB fibers
 // (grid-stride, as many blocks as the device holds at once).  Lane s of the
 // quad loads and quantises feature group s of the symmetric map: s = 0 the
@@ -308,13 +342,13 @@ inline Payload payload_of(void* base, int64_t rows, bool ext_on) {
 // sums (|Xq|^2, |Xq - X|^2, |X|^2) with two lane permutations, the same sums
 // in every lane, and every lane derives the row constant and the error bound
 // from them; lane s then stores codes 4s .. 4s+3 (its own and the first of
-// lane s + 1), so the quad writes the code words whole.  The records are read
-// from memory directly: the wave's sixteen fibers are 4 KB in a row, and the
-// points the quad needs touch every line of them once.  Lane 0 writes the
-// cell key, lanes 1 and 2 the empty result (-1, +inf) when `labels` is not
-// null, lane 2 the constants word (and lane 3 the subject word of a batch).
-// With the length-normalised metric, every lane of the quad also reads the
-// whole record for its arc length.
+// lane s + 1), so the quad writes the code words whole.  Each wave takes 16
+// fibers of a batch: their records (4032 bytes in a row) come in with
+// coalesced 16-byte loads into registers, issued one batch ahead, and go
+// through the wave's part of LDS to the lanes that need them.  Lane 0 writes
+// the cell key, lanes 1 and 2 the empty result (-1, +inf) when `labels` is
+// not null, lane 2 the row constants (with 1-byte codes) and the extra word
+// (arc length, from the record in LDS, and subject).
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));  // 16-byte aligned
 // one point: exactly 12 bytes (a three-element vector type would load 16)
@@ -425,9 +459,15 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
   using T = QTraits<Q>;
   constexpr int EB = T::bytes;
   constexpr int SIDE = 1 << CELL_AXIS_BITS;
+  constexpr int WF = 16;            // fibers per wave and batch
+  constexpr int WV = WF * NF / 4;   // their 16-byte words
+  __shared__ __attribute__((aligned(16))) float s_rec[CF_THREADS / 64][WF * NF];
   const int tid = (int)threadIdx.x;
   const int sl = tid & 3;   // feature group of this lane
   const int fb = tid >> 2;  // fiber within the batch
+  const int lane = tid & 63, wv = tid >> 6;
+  const int fq = lane >> 2;  // fiber within the wave's 16
+  float* const srec = s_rec[wv];
   const int64_t nb = BATCH ? fo.nblk : (n + CF_FIB - 1) / CF_FIB;
   // the frame and the cell grid, once
   const Frame fr = frame(prm, Q);
@@ -444,12 +484,49 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
   const double g = gamma_acc(KPC);
   float e32 = 0.0f;
   SubCursor cursor{};
-  if (BATCH && (int64_t)blockIdx.x < nb) cursor.seek(blockIdx.x, fo.subs, fo.nsub);
+  // the records of this wave's fibers of batch bs: full 16-byte words into
+  // registers (a partial last record's tail words are read when staged)
+  f4u v[4];
+  auto wave_cnt = [&](const BatchSrc& bs) {
+    const int c = bs.cnt - WF * wv;
+    return c < 0 ? 0 : (c > WF ? WF : c);
+  };
+  auto load = [&](const BatchSrc& bs) {
+    const float* src = bs.src + (int64_t)WF * wv * NF;
+    const int n4 = (wave_cnt(bs) * NF) >> 2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane + 64 * u;
+      if (i < n4) v[u] = *(const f4u*)(src + 4 * i);
+    }
+  };
+  BatchSrc bs{};
+  if ((int64_t)blockIdx.x < nb) {
+    if (BATCH) cursor.seek(blockIdx.x, fo.subs, fo.nsub);
+    bs = batch_src<BATCH>(blockIdx.x, fibers, n, cursor);
+    load(bs);
+  }
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    if (BATCH) cursor.advance(b, fo.subs, fo.nsub);
-    const BatchSrc bs = batch_src<BATCH>(b, fibers, n, cursor);
-    if (fb >= bs.cnt) continue;  // the whole quad
-    const float* rec = bs.src + (int64_t)fb * NF;
+    const BatchSrc cur = bs;
+    {
+      const int nfl = wave_cnt(cur) * NF, n4 = nfl >> 2;
+      const float* src = cur.src + (int64_t)WF * wv * NF;
+      wave_lds_sync();  // the previous batch's reads are done
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = lane + 64 * u;
+        if (i < n4) *(f4v*)(srec + 4 * i) = v[u];
+      }
+      if (lane < nfl - 4 * n4) srec[4 * n4 + lane] = src[4 * n4 + lane];
+      wave_lds_sync();
+    }
+    if (b + gridDim.x < nb) {  // the next batch's loads, in flight meanwhile
+      if (BATCH) cursor.advance(b + gridDim.x, fo.subs, fo.nsub);
+      bs = batch_src<BATCH>(b + gridDim.x, fibers, n, cursor);
+      load(bs);
+    }
+    if (fb >= cur.cnt) continue;  // the whole quad
+    const float* rec = srec + fq * NF;
     const Pt3 A = *(const Pt3*)(rec + 3 * pi);
     const Pt3 B = *(const Pt3*)(rec + 3 * pj);
     // features: the center point's coordinates, or a pair's midpoint and
@@ -507,8 +584,8 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
     }
     // 2-byte codes: the error bound in the slot of feature 15
     if (EB == 2 && sl == 3) o3 = (uint32_t)__half_as_ushort(__float2half_ru(er));
-    const int64_t f = bs.row + fb;     // payload row
-    const int64_t loc = bs.local + fb;  // index within the subject
+    const int64_t f = cur.row + fb;     // payload row
+    const int64_t loc = cur.local + fb;  // index within the subject
     uint8_t* C = fo.pay.codes + f * (16 * EB);
     if (EB == 2)
       *(uint2*)(C + 8 * sl) = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
@@ -527,30 +604,18 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
     } else if (sl == 2) {
       float len = 0.0f;
       if (TN) {
-        float r[NF];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) {
-          const f4u v = *(const f4u*)(rec + 4 * k);
-          r[4 * k] = v.x;
-          r[4 * k + 1] = v.y;
-          r[4 * k + 2] = v.z;
-          r[4 * k + 3] = v.w;
-        }
-        r[60] = rec[60];
-        r[61] = rec[61];
-        r[62] = rec[62];
-        len = arc_length(r);
+        len = arc_length(rec);
       }
       if (EB == 1) fo.pay.cst[f] = make_float2(nh, er);
       if (BATCH || TN)
-        fo.pay.ext[f] = make_float4(len, __int_as_float(BATCH ? bs.sub : 0),
+        fo.pay.ext[f] = make_float4(len, __int_as_float(BATCH ? cur.sub : 0),
                                     __int_as_float(BATCH ? (int32_t)loc : 0), 0.0f);
     }
     if (BATCH) {
       if (sl == 1)
-        for (int32_t a = 0; a < fo.na; ++a) fo.out_lab[bs.sub * fo.na + a][loc] = -1;
+        for (int32_t a = 0; a < fo.na; ++a) fo.out_lab[cur.sub * fo.na + a][loc] = -1;
       else if (sl == 2)
-        for (int32_t a = 0; a < fo.na; ++a) fo.out_dst[bs.sub * fo.na + a][loc] = __builtin_inff();
+        for (int32_t a = 0; a < fo.na; ++a) fo.out_dst[cur.sub * fo.na + a][loc] = __builtin_inff();
     } else if (fo.labels) {
       if (sl == 1) fo.labels[f] = -1;
       else if (sl == 2) fo.dists[f] = __builtin_inff();
@@ -562,8 +627,10 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
               __float_as_uint(e32));
 }
 
-// Blocks of cull_fiber_kernel<Q, BATCH, TN> that the device holds at once
-// (register-bound), queried once per process and kernel.
+// Blocks of cull_fiber_kernel<Q, BATCH, TN> launched: half of what the
+// device holds at once (queried once per process and kernel); with every
+// slot filled the streams of reads and writes are spread over a wider
+// window of memory and the kernel ran about a tenth slower.
 template <int Q, bool BATCH, bool TN>
 int64_t cf_grid() {
   static std::atomic<int64_t> g{0};
@@ -576,19 +643,12 @@ int64_t cf_grid() {
                                                      CF_THREADS, 0) != hipSuccess ||
         cus <= 0 || per <= 0)
       return 1024;
-    v = (int64_t)cus * per;
+    v = std::max<int64_t>((int64_t)cus * per / 2, cus);
     g.store(v, std::memory_order_relaxed);
   }
   return v;
 }
 
-// Order the wave's LDS writes before its later LDS reads (lanes read what
-// other lanes of the same wave wrote).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Codes as order-preserving unsigned 16-bit values, two per word: 2-byte
 // codes (fp16, bf16: sign and magnitude) map h to h | 0x8000 when positive
@@ -1245,9 +1305,63 @@ int grow_sort(PrefilterBuf& pb, int64_t nk) {
   return rc;
 }
 
-// Centroid order: cell keys of the prepared records, then the sort.
+// Centroid order for up to RANK_MAX centroids by counting ranks: with the
+// unique composite keys c = cell << 15 | index (their order is the stable
+// order by cell), the sorted position of centroid i is the number of c below
+// its own.  rank_count_kernel: block (x, y) counts, for its 256 centroids i,
+// the c of centroid tile y (1024 of them, staged in LDS) below c_i, into
+// part[y][i]; rank_place_kernel adds the parts and writes cperm[pos] = i.
+// Plain integer sums, so the order is deterministic.
+constexpr int RANK_MAX = 16384;
+constexpr int RANK_TILE = 1024;
+__device__ __forceinline__ uint32_t comp_key(const float* __restrict__ cprep, int32_t i,
+                                             const PfParams* __restrict__ prm) {
+  return (center_cell(cprep + (int64_t)i * CREC, prm) << 15) | (uint32_t)i;
+}
+__global__ __launch_bounds__(256) void rank_count_kernel(const float* __restrict__ cprep, int32_t m,
+                                                         const PfParams* __restrict__ prm,
+                                                         uint32_t* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint32_t s_c[RANK_TILE];
+  const int tid = (int)threadIdx.x;
+  const int32_t j0 = (int32_t)blockIdx.y * RANK_TILE;
+  for (int k = tid; k < RANK_TILE; k += 256) {
+    const int32_t j = j0 + k;
+    s_c[k] = j < m ? comp_key(cprep, j, prm) : 0xFFFFFFFFu;  // past m: above every key
+  }
+  const int32_t i = (int32_t)blockIdx.x * 256 + tid;
+  const uint32_t ci = i < m ? comp_key(cprep, i, prm) : 0u;
+  __syncthreads();
+  uint32_t cnt = 0;
+#pragma unroll 8
+  for (int k = 0; k < RANK_TILE; k += 4) {
+    const uint4 v = *(const uint4*)&s_c[k];
+    cnt += (v.x < ci) + (v.y < ci) + (v.z < ci) + (v.w < ci);
+  }
+  if (i < m) part[(int64_t)blockIdx.y * m + i] = cnt;
+}
+__global__ __launch_bounds__(256) void rank_place_kernel(const uint32_t* __restrict__ part,
+                                                         int32_t m, int32_t tiles,
+                                                         int32_t* __restrict__ cperm) {
+  const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (i >= m) return;
+  uint32_t pos = 0;
+  for (int32_t y = 0; y < tiles; ++y) pos += part[(int64_t)y * m + i];
+  cperm[pos] = i;  // pos < m: the c are distinct
+}
+
+// Centroid order: by counting ranks for up to RANK_MAX centroids, else cell
+// keys of the prepared records and the radix sort.
 int sort_centroids(const float* cprep, int32_t m, const PfParams* prm, PrefilterBuf& pb, int64_t nk,
                    int32_t* cperm, hipStream_t s) {
+  if (m <= RANK_MAX) {
+    const int32_t tiles = (m + RANK_TILE - 1) / RANK_TILE;
+    if (grow(&pb.rank, &pb.rank_bytes, (size_t)tiles * m * sizeof(uint32_t))) return -3;
+    uint32_t* part = (uint32_t*)pb.rank;
+    rank_count_kernel<<<dim3((unsigned)((m + 255) / 256), (unsigned)tiles), 256, 0, s>>>(
+        cprep, m, prm, part);
+    rank_place_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(part, m, tiles, cperm);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   uint32_t* keys_a = (uint32_t*)pb.keys;
   int32_t* vals_a = (int32_t*)pb.vals;
   cell_key_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(cprep, m, CREC, prm, keys_a);
@@ -1286,7 +1400,10 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   int32_t* cperm = (int32_t*)pb.cperm;
   if (launch_pf_setup(prm, cprep, m, s)) return -1;
   // centroids: their order (unless the prepared atlas holds it)
-  if (!cperm_cached && sort_centroids(cprep, m, prm, pb, nk, cperm, s)) return -1;
+  if (!cperm_cached) {
+    rc = sort_centroids(cprep, m, prm, pb, nk, cperm, s);
+    if (rc) return rc;
+  }
   // fibers: payloads and cells in input order, then the permutation
   {
     const int64_t nb = (n + CF_FIB - 1) / CF_FIB;

@@ -38,6 +38,8 @@ struct PrefilterBuf {
   size_t hist_bytes = 0;
   void* cperm = nullptr;  // sorted column -> centroid
   size_t cperm_bytes = 0;
+  void* rank = nullptr;   // partial rank counts of the centroid order
+  size_t rank_bytes = 0;
 };
 
 struct PfParams;
