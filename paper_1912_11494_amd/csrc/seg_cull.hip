@@ -781,6 +781,7 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
                                                           uint8_t* __restrict__ feat,
                                                           float* __restrict__ cb,
                                                           int32_t* __restrict__ ccent,
+                                                          float* __restrict__ csort,
                                                           float* __restrict__ tbox,
                                                           float* __restrict__ sbox) {
   using T = QTraits<Q>;
@@ -803,8 +804,12 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
     } else {
       const int32_t c = cperm[col];
       ccent[col] = c;
-      cb[col] = column_row<Q, MAP_SYM, KPC>(cprep + (int64_t)c * CREC, false, prm, row, lo, hi,
-                                            &r2);
+      const float* rec = cprep + (int64_t)c * CREC;
+      cb[col] = column_row<Q, MAP_SYM, KPC>(rec, false, prm, row, lo, hi, &r2);
+      // the record in column order, for the exact stage
+#pragma unroll
+      for (int k = 0; k < CREC; k += 4)
+        *(float4*)(csort + (int64_t)col * CREC + k) = *(const float4*)(rec + k);
     }
   }
   half_wave_box(lo, hi, BOXD);
@@ -853,7 +858,7 @@ struct CullJob {
   int32_t nsuper;
   const float* fibers;   // the subject's fiber records (input order)
   int64_t n;
-  const float* cprep;    // prepared centroid records (63 coordinates + T2)
+  const float* csort;    // the prepared records (63 coordinates + T2) in column order
   const int32_t* bid;    // bundle of each prepared centroid
   int32_t* labels;       // written for fibers with an accepted centroid
   float* dists;
@@ -1101,11 +1106,12 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
         const bool act = j < cnt;
         const uint32_t e = act ? s_q[wave][j] : 0u;
         const int slot = (int)(e & 63u);
-        const uint32_t c = e >> 6;
+        const uint32_t col = e >> 6;
+        const uint32_t c = (uint32_t)job.ccent[col];
         const int32_t f = s_idx[wave][slot];
         const float* ar = frec(slot, f);
         float D, v;
-        const bool ok = exact_pair<true>(ar, job.cprep + (size_t)c * CREC, act, D, sc, mt.flags);
+        const bool ok = exact_pair<true>(ar, job.csort + (size_t)col * CREC, act, D, sc, mt.flags);
         if (ok && variant_value(D, c, s_len[wave][slot], mt, v)) fold(slot, f, c, v);
       }
     } else {
@@ -1113,12 +1119,13 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
       for (uint32_t j0 = 0; j0 < cnt; j0 += 16) {
         const uint32_t j = j0 + (uint32_t)(lane >> 2);
         const bool act = j < cnt;
-        const uint32_t e = act ? s_q[wave][j] : 0u;  // inactive quads read row 0, centroid 0
+        const uint32_t e = act ? s_q[wave][j] : 0u;  // inactive quads read row 0, column 0
         const int slot = (int)(e & 63u);
-        const uint32_t c = e >> 6;
+        const uint32_t col = e >> 6;
+        const uint32_t c = (uint32_t)job.ccent[col];  // (loads with the record)
         const int32_t f = s_idx[wave][slot];
         float D, v;
-        const bool ok = quad_pair(frec(slot, f), job.cprep + (size_t)c * CREC, sl, D, mt.flags);
+        const bool ok = quad_pair(frec(slot, f), job.csort + (size_t)col * CREC, sl, D, mt.flags);
         if (sl == 0 && act && ok && variant_value(D, c, s_len[wave][slot], mt, v))
           fold(slot, f, c, v);
       }
@@ -1131,8 +1138,8 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   // rows are NaN and never pass
   // (row r of the lane's outputs is row 8 (r / 4) + 4 half + r % 4 of the
   // group: the entry of output r is ebase + 8 (r / 4) + r % 4)
-  auto extract = [&](const f32x16& a, int g, uint32_t cent, float cbv) {
-    const uint32_t ebase = (cent << 6) | (uint32_t)(g * 32 + 4 * half);
+  auto extract = [&](const f32x16& a, int g, uint32_t col, float cbv) {
+    const uint32_t ebase = (col << 6) | (uint32_t)(g * 32 + 4 * half);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const uint32_t e = ebase + (uint32_t)(8 * (r >> 2) + (r & 3));
@@ -1144,10 +1151,10 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
     }
   };
   auto cload = [&](uint32_t i, FT& b, float& cb, uint32_t& cn) {
-    const int64_t col = (int64_t)s_cand[wave][i] * 32 + l31;
-    b = *(const FT*)(job.cfeat + col * (KPC * EB) + 8 * half * EB);
+    const uint32_t col = s_cand[wave][i] * 32u + (uint32_t)l31;
+    b = *(const FT*)(job.cfeat + (int64_t)col * (KPC * EB) + 8 * half * EB);
     cb = job.cbias[col];
-    cn = (uint32_t)job.ccent[col];
+    cn = col;
   };
 
   // gap^2 of box row `i` of a [TROWS][cnt] struct-of-arrays table against
@@ -1179,14 +1186,14 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
     wave_lds_sync();
     if (STATS && lane == 0)
       atomicAdd(counters + 5, (unsigned long long)nc * (g1 ? 2u : 1u));
-    auto step = [&](const FT& b, float cbv, uint32_t cent) {
+    auto step = [&](const FT& b, float cbv, uint32_t col) {
       if (qn > (uint32_t)(CQ - CQ_ROOM)) {
         drain(qn);
         qn = 0;
       }
       {
         const f32x16 a = Frag<Q>::mfma(afr[0], b, negh(0));
-        if (wave_any(max16(a) >= cbv)) extract(a, 0, cent, cbv);
+        if (wave_any(max16(a) >= cbv)) extract(a, 0, col, cbv);
       }
       if (g1) {
         if (qn > (uint32_t)(CQ - CQ_ROOM)) {
@@ -1194,7 +1201,7 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
           qn = 0;
         }
         const f32x16 a = Frag<Q>::mfma(afr[1], b, negh(1));
-        if (wave_any(max16(a) >= cbv)) extract(a, 1, cent, cbv);
+        if (wave_any(max16(a) >= cbv)) extract(a, 1, col, cbv);
       }
     };
     FT b0, b1, b2;
@@ -1383,7 +1390,7 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   rc = rc ? rc : grow_sort(pb, nk);
   rc = rc ? rc : grow(&pb.cperm, &pb.cperm_bytes, (size_t)std::max<int32_t>(m, 1) * 4);
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
-                      (size_t)ncols_pad * (KPC * EB + 2 * sizeof(float)));
+                      (size_t)ncols_pad * (CREC_BYTES + KPC * EB + 2 * sizeof(float)));
   const int32_t nsuper = (ncols_pad + 255) / 256;  // one column block each
   rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes,
                       (size_t)TROWS * (ntiles + nsuper) * sizeof(float));
@@ -1391,7 +1398,9 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
   PfParams* prm = (PfParams*)pb.emax;
   const Payload pay = payload_of(pb.fib_feat, n, (mt.flags & MF_TN) != 0);
-  uint8_t* cfeat = (uint8_t*)pb.cen_feat;
+  // columns: records in column order, codes, constants, centroids
+  float* csort = (float*)pb.cen_feat;
+  uint8_t* cfeat = (uint8_t*)(csort + (size_t)ncols_pad * CREC);
   float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
   int32_t* ccent = (int32_t*)(cbias + ncols_pad);
   uint32_t* keys_a = (uint32_t*)pb.keys;
@@ -1424,10 +1433,10 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   float* tbox = (float*)pb.tbox;
   float* sbox = tbox + (size_t)TROWS * ntiles;
   cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, s>>>(
-      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent, tbox,
-      sbox);
+      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent, csort,
+      tbox, sbox);
   const CullJob job{pay,    perm,  prm,     cfeat,   cbias,   ccent, tbox, sbox, ntiles,
-                    nsuper, fibers, n,      cprep,   bid,     labels,  dists, nullptr, nullptr,
+                    nsuper, fibers, n,      csort,   bid,     labels,  dists, nullptr, nullptr,
                     nullptr, 0, 0};
   const MultiOut mout = mo ? *mo : MultiOut{nullptr, 0, nullptr, nullptr};
   const unsigned blocks = (unsigned)((n + 64 * CW - 1) / (64 * CW));
@@ -1497,7 +1506,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)rows * PAY_BYTES);
   rc = rc ? rc : grow_sort(pb, nk);
   rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
-                      (size_t)cpad_max * (KPC * EB + 2 * sizeof(float)));
+                      (size_t)cpad_max * (CREC_BYTES + KPC * EB + 2 * sizeof(float)));
   rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes,
                       (size_t)TROWS * (tiles_max + super_max) * sizeof(float));
   const size_t tab = (size_t)nsub * sizeof(SubDev) + olab.size() * 2 * sizeof(void*);
@@ -1531,7 +1540,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   }
   PfParams* prm = (PfParams*)pb.emax;
   const Payload pay = payload_of(pb.fib_feat, rows, true);
-  uint8_t* cfeat = (uint8_t*)pb.cen_feat;
+  float* const csort = (float*)pb.cen_feat;
   uint32_t* keys_a = (uint32_t*)pb.keys;
   int32_t* vals_a = (int32_t*)pb.vals;
   int32_t* perm = vals_a + nk;
@@ -1559,13 +1568,14 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
         const int32_t ncols_pad = (m + 31) / 32 * 32;
         const int32_t ntiles = ncols_pad / 32;
         const int32_t nsuper = (ncols_pad + 255) / 256;
+        uint8_t* cfeat = (uint8_t*)(csort + (size_t)ncols_pad * CREC);
         float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
         int32_t* ccent = (int32_t*)(cbias + ncols_pad);
         float* sbox = tbox + (size_t)TROWS * ntiles;
         cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(
-            at[a].cprep, m, ncols_pad, cperms[a], prm, cfeat, cbias, ccent, tbox, sbox);
+            at[a].cprep, m, ncols_pad, cperms[a], prm, cfeat, cbias, ccent, csort, tbox, sbox);
         const CullJob job{pay,    perm,    prm,      cfeat,      cbias, ccent,  tbox,
-                          sbox,   ntiles,  nsuper,   nullptr,    ch.rows, at[a].cprep,
+                          sbox,   ntiles,  nsuper,   nullptr,    ch.rows, csort,
                           at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a};
         const MultiOut mout{nullptr, 0, nullptr, nullptr};
         cull_kernel<Q, false, false, true>
