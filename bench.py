@@ -40,6 +40,8 @@ WORKLOADS = {
     "paper-4145k-x-10k": "4,145,000 fibers x 10,000 centroids (100 bundles x 100, 20-80 mm), "
                          "21 pts fp32",
     "large-10M-x-20k": "10,000,000 fibers x 20,000 centroids (200 bundles x 100), 21 pts fp32",
+    "clustered-4145k-x-10k": "4,145,000 fibers x 10,000 centroids (100 bundles x 100), 80% of "
+                             "the fibers around 5 of the bundles, 21 pts fp32",
 }
 # kernels whose HBM traffic is summarised: counter-file kernel-name prefix -> key
 TRAFFIC_KERNELS = [("seg::(anonymousnamespace)::cull_kernel<0,", "cull_kernel:bf16"),
@@ -360,12 +362,15 @@ def bench_batch(args, atl, subs, P, hip):
             "dist_diffs_vs_sequential_plain": {k: ndiff(o, 1) for k, o in outs_of.items()}}
 
 
-def bench_large(args, at, fib, P, hip):
-    """The large subject (10M fibers x 20,000 centroids): the tile-culled fp16,
-    bf16 and fp8 forms against the plain form, with survivors per fiber,
-    accepted pairs (a pair a prefilter dropped would be missing from its
-    count: false discards = plain's accepted pairs minus the mode's) and
-    label / distance differences against the plain form."""
+def bench_subject(args, wl, at, fib, P, hip, modes_list, tag):
+    """One more single-subject workload (the large 10M x 20,000 subject, the
+    clustered-density subject): each mode timed against the plain form, with
+    survivors per fiber, the fraction of pairs the bound was evaluated on,
+    exact-stage drains per wave of 64 sorted rows (the survivor queue drains
+    once at the end, and again each time it fills), accepted pairs (a pair a
+    prefilter dropped would be missing from its count: false discards =
+    plain's accepted pairs minus the mode's) and label / distance differences
+    against the plain form.  ``dense`` runs one timed step."""
     import torch
 
     d = torch.device("cuda:0")
@@ -376,8 +381,9 @@ def bench_large(args, at, fib, P, hip):
     N, M = fib.shape[0], at.n_centroids
     steps, warmup = max(1, args.steps // 4), 1
     modes, outs = {}, {}
-    for mode in ("fp16", "bf16", "fp8", "plain"):
-        r, out = time_mode(P, hip, f, c, b, t, mode, steps, warmup)
+    for mode in modes_list:
+        ms, wu = (1, 0) if mode == "dense" else (steps, warmup)
+        r, out = time_mode(P, hip, f, c, b, t, mode, ms, wu)
         P.segment(f, c, b, t, mode=mode, stats=True)
         st = P.query_stats()
         modes[mode] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
@@ -385,21 +391,25 @@ def bench_large(args, at, fib, P, hip):
                        "fibers_per_s": N / (r["ms_per_step"] * 1e-3),
                        "survivors_per_fiber": st["filter_pass"] / N,
                        "accepted_pairs": st["accepted"],
-                       "bound_pairs_frac": st["bound_pairs"] / st["pairs"]}
+                       "bound_pairs_frac": st["bound_pairs"] / st["pairs"],
+                       "exact_drains_per_wave": st["drains"] / ((N + 63) // 64)}
         outs[mode] = out
-        log(f"large {mode}: {r['ms_per_step']:.3f} ms/step, "
+        log(f"{tag} {mode}: {r['ms_per_step']:.3f} ms/step, "
             f"{modes[mode]['survivors_per_fiber']:.2f} survivors per fiber")
     ref = outs["plain"]
     for mode, x in modes.items():
         x["label_diffs_vs_plain"] = int((outs[mode][0] != ref[0]).sum().item())
         x["dist_diffs_vs_plain"] = int((outs[mode][1] != ref[1]).sum().item())
-        x["false_discards"] = modes["plain"]["accepted_pairs"] - x["accepted_pairs"]
+        # (the dense form evaluates every pair exactly and counts no stages)
+        x["false_discards"] = (None if mode == "dense" else
+                               modes["plain"]["accepted_pairs"] - x["accepted_pairs"])
+        if mode == "dense":
+            x["accepted_pairs"] = None
     foot = footprint(P, f, c, b, t, outs["fp16"])
     del f, c, b, t, outs, ref
     torch.cuda.empty_cache()
-    return {"workload": f"large-10M-x-20k: {WORKLOADS['large-10M-x-20k']}", "fibers": N,
-            "centroids": M, "steps": steps, "modes": modes, "headline": "fp16",
-            "device_bytes": foot}
+    return {"workload": f"{wl}: {WORKLOADS[wl]}", "fibers": N, "centroids": M, "steps": steps,
+            "modes": modes, "headline": "fp16", "device_bytes": foot}
 
 
 def footprint(P, f, c, b, t, out):
@@ -633,6 +643,9 @@ def main():
                     help="skip the batch workload leg (16 subjects x 2 atlases)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-subject leg (10M fibers x 20,000 centroids)")
+    ap.add_argument("--no-clustered", action="store_true",
+                    help="skip the clustered-density leg (80%% of the fibers around 5%% of the "
+                         "bundles)")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes drawing the synthetic inputs; 1 under a profiler, whose "
                          "preloaded library has initialised the GPU before this script runs")
@@ -691,7 +704,15 @@ def main():
     fib = synth.make_fibers([at], subj, synth.workload_seed(wl), workers=W)
     log(f"generated {wl}: {fib.shape[0]} fibers x {at.n_centroids} centroids "
         f"in {time.time() - t0:.1f}s")
-    large_in = batch_in = None
+    large_in = batch_in = clus_in = None
+    if wl == "paper-4145k-x-10k" and not args.no_clustered:
+        wl_c = "clustered-4145k-x-10k"
+        at_c = synth.workload_atlases(wl_c)[0]
+        t0 = time.time()
+        fib_c = synth.make_fibers([at_c], synth.workload_subjects(wl_c)[0],
+                                  synth.workload_seed(wl_c), workers=W)
+        log(f"generated {wl_c}: {fib_c.shape[0]} fibers in {time.time() - t0:.1f}s")
+        clus_in = (at_c, fib_c)
     if wl == "paper-4145k-x-10k" and not args.no_large:
         wl_l = "large-10M-x-20k"
         at_l = synth.workload_atlases(wl_l)[0]
@@ -823,9 +844,14 @@ def main():
     resample = None if args.no_resample else bench_resample(P, hip, f, at, c, b, t, wl, head,
                                                             args, N, np)
 
-    large = batch = None
+    large = batch = clustered = None
+    if clus_in is not None:
+        clustered = bench_subject(args, "clustered-4145k-x-10k", *clus_in, P, hip,
+                                  ("fp16", "plain", "dense"), "clustered")
+        del clus_in
     if large_in is not None:
-        large = bench_large(args, *large_in, P, hip)
+        large = bench_subject(args, "large-10M-x-20k", *large_in, P, hip,
+                              ("fp16", "bf16", "fp8", "plain"), "large")
         del large_in
     if batch_in is not None:
         batch = bench_batch(args, *batch_in, P, hip)
@@ -866,6 +892,7 @@ def main():
         "resample": resample,
         "device_bytes": foot,
         "large": large,
+        "clustered": clustered,
         "batch": batch,
         "cpu_baseline": cpu,
         "source_hash": source_hash(),

@@ -40,7 +40,7 @@ from __future__ import annotations
 
 import sys
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -70,6 +70,10 @@ class SubjectSpec:
     sigma: float
     # fraction of fibers copied from each atlas (one entry per atlas)
     matched: Sequence[float]
+    # clustered density: (fiber fraction, bundle fraction): that fraction of
+    # the fibers are copies of centroids of the first round(bundle fraction x
+    # bundles) bundles of the first atlas; `matched` applies to the rest
+    hot: Optional[Tuple[float, float]] = None
 
 
 @dataclass
@@ -115,6 +119,13 @@ WORKLOADS = {
         seed=15494,
         atlases=[AtlasSpec(200, 100, thr_lo=5.0, thr_hi=8.0, **_SHORT)],
         subjects=[SubjectSpec(10_000_000, 2.0, (0.3,))],
+    ),
+    # the paper-scale atlas and subject size with 80% of the fibers packed
+    # around 5% of the bundles (dense regions, as near the cortex)
+    "clustered-4145k-x-10k": dict(
+        seed=17494,
+        atlases=[AtlasSpec(100, 100, thr_lo=5.0, thr_hi=8.0, **_SHORT)],
+        subjects=[SubjectSpec(4_145_000, 2.0, (0.3,), hot=(0.8, 0.05))],
     ),
     "batch-16-subjects-x-2-atlases": dict(
         seed=16494,
@@ -256,26 +267,27 @@ def make_atlas(spec: AtlasSpec, seed: int) -> Atlas:
 
 
 def _fiber_chunk(atlases: Sequence[Atlas], matched: Sequence[float], sigma: float,
-                 n: int, rng: np.random.Generator) -> np.ndarray:
+                 n: int, rng: np.random.Generator, hot=None) -> np.ndarray:
+    n_all = n
+    hot_part = None
+    if hot is not None:
+        # copies of the hot bundles' centroids (ids are bundle-major)
+        n_hot = int(round(hot[0] * n))
+        at0 = atlases[0]
+        per = at0.spec.per_bundle if at0.spec else int(np.bincount(at0.bundle_id).max())
+        nb_hot = max(1, int(round(hot[1] * (int(at0.bundle_id.max()) + 1))))
+        hot_part = _copies(at0, rng.integers(0, nb_hot * per, n_hot), sigma, rng)
+        n -= n_hot
     counts = [int(round(f * n)) for f in matched]
     n_match = sum(counts)
     if n_match > n:
         raise ValueError("matched fractions exceed 1")
-    parts = []
+    parts = [] if hot_part is None else [hot_part]
     for atlas, cnt in zip(atlases, counts):
         if cnt == 0:
             continue
         pick = rng.integers(0, atlas.n_centroids, cnt)
-        base = atlas.centroids[pick].astype(np.float64)
-        knots = rng.normal(0.0, sigma, (cnt, 4, 3))
-        t = np.arange(N_POINTS) / (N_POINTS - 1)
-        seg = np.minimum((t * 3).astype(int), 2)
-        w = (t * 3 - seg)[None, :, None]
-        disp = knots[:, seg, :] * (1 - w) + knots[:, seg + 1, :] * w
-        f = base + disp
-        flip = rng.random(cnt) < 0.5
-        f[flip] = f[flip, ::-1, :]
-        parts.append(f)
+        parts.append(_copies(atlas, pick, sigma, rng))
     n_free = n - n_match
     if n_free:
         # each unmatched fiber takes the length range of a uniformly chosen atlas
@@ -289,8 +301,24 @@ def _fiber_chunk(atlases: Sequence[Atlas], matched: Sequence[float], sigma: floa
                 free[sel] = bezier_curves(rng, sel.size, lo, hi)
         parts.append(free)
     allf = np.concatenate(parts, 0) if parts else np.empty((0, N_POINTS, 3))
-    allf = allf[rng.permutation(n)]
+    allf = allf[rng.permutation(n_all)]
     return allf.astype(np.float32)
+
+
+def _copies(atlas: Atlas, pick: np.ndarray, sigma: float, rng: np.random.Generator) -> np.ndarray:
+    """Copies of centroids ``pick`` with a smooth displacement (4 knots of
+    N(0, sigma) per axis, linear between them), half of them reversed."""
+    cnt = pick.size
+    base = atlas.centroids[pick].astype(np.float64)
+    knots = rng.normal(0.0, sigma, (cnt, 4, 3))
+    t = np.arange(N_POINTS) / (N_POINTS - 1)
+    seg = np.minimum((t * 3).astype(int), 2)
+    w = (t * 3 - seg)[None, :, None]
+    disp = knots[:, seg, :] * (1 - w) + knots[:, seg + 1, :] * w
+    f = base + disp
+    flip = rng.random(cnt) < 0.5
+    f[flip] = f[flip, ::-1, :]
+    return f
 
 
 def _chunk_job(args):
@@ -298,7 +326,7 @@ def _chunk_job(args):
     lo = c * CHUNK
     n = min(CHUNK, subject.n_fibers - lo)
     return _fiber_chunk(atlases, subject.matched, subject.sigma, n,
-                        _rng(seed, 1, subject_idx, c))
+                        _rng(seed, 1, subject_idx, c), subject.hot)
 
 
 def gpu_in_use() -> bool:

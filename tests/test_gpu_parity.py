@@ -266,12 +266,16 @@ def test_stats_and_determinism(seg):
         assert torch.equal(l2, lab) and torch.equal(d2, dist)
 
 
-@pytest.mark.workloads("small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k", "large-10M-x-20k")
+@pytest.mark.workloads("small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k", "large-10M-x-20k",
+                       "clustered-4145k-x-10k")
 @pytest.mark.parametrize("wl", ["small-20k-x-800", "exact-1M-x-3600", "paper-4145k-x-10k",
-                                "large-10M-x-20k"])
+                                "large-10M-x-20k", "clustered-4145k-x-10k"])
 def test_full_size_sampled(seg, wl):
     """Full-size workload in the launch configuration the benchmark times;
-    the oracle recomputes a fixed sample of fibers one by one."""
+    the oracle recomputes a fixed sample of fibers one by one.  The clustered
+    subject packs 80% of its fibers around 5 of the 100 bundles, so its
+    sorted waves hold many survivors (the exact stage drains its queue many
+    times per wave)."""
     import torch
 
     at = synth.workload_atlases(wl)[0]
@@ -283,7 +287,7 @@ def test_full_size_sampled(seg, wl):
     idx = np.concatenate([idx, np.arange(subj.n_fibers - 200, subj.n_fibers)])
     o32 = oracle.segment_f32(fib[idx], at.centroids, at.bundle_id, at.thresholds, mode=oracle.CUT)
     for mode in ALL_MODES:
-        if mode == "dense" and (wl.startswith("paper") or wl.startswith("large")):
+        if mode == "dense" and wl.split("-")[0] in ("paper", "large", "clustered"):
             continue  # 0.2-0.8 s of GPU time; covered by the smaller cases
         log(f"full size {wl} mode {mode}")
         lab, dist = seg.segment(f, c, b, t, mode=mode)
