@@ -767,6 +767,7 @@ def main():
         r["stats"] = st
         modes[spec] = r
         outs[spec] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+        r["labelled"] = int((outs[spec][0] >= 0).sum())
         log(f"mode {spec}: {r['ms_per_step']:.3f} ms/step, kernel {r['kernel_ms']:.3f} ms, "
             f"{r['pairs_per_s']:.3e} pairs/s")
 
@@ -797,12 +798,34 @@ def main():
                 "kernel_ms": x["kernel_ms"],
                 "bound_pairs_frac": x["stats"]["bound_pairs"] / x["stats"]["pairs"]}
 
+    def cull_roofline(spec):
+        """The tile-culled kernel against HBM: per launch, each sorted row's
+        permutation entry and payload row (4 + 32 bytes; 4 + 16 + 8 with
+        1-byte codes), the record of each fiber with a survivor (252 bytes),
+        and the label and distance of each labelled fiber (8 bytes).  The
+        centroid records it re-reads are cache-resident (2.5 MB)."""
+        mode = spec.split(":")[0]
+        x = modes[spec]
+        st = x["stats"]
+        row = 4 + (28 if mode == "fp8" else 36)
+        alg = N * row + st["survivor_rows"] * 252 + x["labelled"] * 8
+        ach = alg / (x["kernel_ms"] * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": ach / PEAK_HBM, "traffic": traffic_for(f"cull_kernel:{mode}"),
+                "kernel": "cull_kernel", "kernel_ms": x["kernel_ms"], "alg_bytes": alg,
+                "bound_pairs_frac": st["bound_pairs"] / st["pairs"],
+                "mfma": {k: v for k, v in mfma_roofline(spec).items()
+                         if k in ("achieved", "peak", "unit", "frac")}}
+
     if head in ("dense", "plain"):
         ach = alg_flops(head, r["stats"], N, M) / (r["kernel_ms"] * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32, "unit": "TFLOP/s",
                     "frac": ach / PEAK_FP32, "traffic": traffic_for(f"{head}_kernel"),
                     "kernel": f"{head}_kernel", "kernel_ms": r["kernel_ms"]}
         dtype = "f32"
+    elif modes[head]["stats"]["bound_pairs"] < modes[head]["stats"]["pairs"]:
+        roofline = cull_roofline(head)
+        dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head.split(":")[0], "bf16+f32")
     else:
         roofline = mfma_roofline(head)
         dtype = {"fp8": "fp8+f32", "fp16": "f16+f32"}.get(head.split(":")[0], "bf16+f32")

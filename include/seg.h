@@ -140,6 +140,9 @@ typedef struct seg_stats {
   int64_t bound_pairs;     /* pairs the first cut evaluated one by one: N * M,
                               except for the tile-culled prefilter, which
                               skips whole (32 fibers x 32 columns) tiles */
+  int64_t survivor_rows;   /* tile-culled prefilter: fibers with at least one
+                              pair past the bound (the fiber records its exact
+                              stage reads); -1 for the other forms */
 } seg_stats;
 
 /* Default options (mode SEG_PLAIN, no validation, library tiles, no stats,

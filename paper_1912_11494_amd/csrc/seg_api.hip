@@ -910,6 +910,7 @@ int seg_query_stats(seg_stats* out) {
   out->accepted = (int64_t)c[3];
   out->drains = (int64_t)c[4];
   out->bound_pairs = t_stats_culled ? (int64_t)c[5] * 1024 : t_stats_pairs;
+  out->survivor_rows = t_stats_culled ? (int64_t)c[6] : -1;
   out->labelled = -1;
   return SEG_OK;
 }

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
         len = arc_length(rec);
       }
       if (EB == 1) fo.pay.cst[f] = make_float2(nh, er);
-      if (BATCH || TN)
+      if (fo.pay.ext_on)
         fo.pay.ext[f] = make_float4(len, __int_as_float(BATCH ? cur.sub : 0),
                                     __int_as_float(BATCH ? (int32_t)loc : 0), 0.0f);
     }
@@ -845,6 +845,11 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
   }
 }
 
+// A chunk of at most this many subjects finds a row's subject from the
+// subjects' first rows; a larger chunk (or the length-normalised metric)
+// carries subject, index and arc length in the extra payload word.
+constexpr int32_t BATCH_SUBS = 16;
+
 struct CullJob {
   Payload pay;           // fiber payloads in input order
   const int32_t* perm;   // sorted position -> input index
@@ -867,6 +872,7 @@ struct CullJob {
   int32_t* const* out_lab;  // subject s against atlas a at s * na + a
   float* const* out_dst;
   int32_t na, atlas;
+  int32_t nsub;  // subjects of the chunk (with no extra payload word: at most BATCH_SUBS)
 };
 
 constexpr int CW = 4;          // waves per block (each works on its own)
@@ -970,6 +976,7 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   __shared__ uint32_t s_q[CW][CQ];                             // centroid << 6 | row
   __shared__ unsigned long long s_best[CW][64];                // argmin key of each row
   __shared__ uint32_t s_box[CW][16];                           // union box (16-bit codes)
+  __shared__ uint32_t s_hit[CW][STATS ? 64 : 1];               // rows with a survivor (STATS)
   const int lane = (int)(threadIdx.x & 63);
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int half = lane >> 5;
@@ -993,12 +1000,33 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   }
   float2 cst[2] = {make_float2(0.0f, 0.0f), make_float2(0.0f, 0.0f)};  // 1-byte codes
   float4 ext[2] = {make_float4(0.0f, 0.0f, 0.0f, 0.0f), make_float4(0.0f, 0.0f, 0.0f, 0.0f)};
-  const bool with_ext = BATCH || job.pay.ext_on;
+  const bool with_ext = job.pay.ext_on;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     afr[g] = *(const FT*)(job.pay.codes + (int64_t)prow[g] * (16 * EB) + 8 * half * EB);
     if (EB == 1) cst[g] = job.pay.cst[prow[g]];
     if (with_ext) ext[g] = job.pay.ext[prow[g]];
+  }
+  if (BATCH && !with_ext) {
+    // a chunk of at most BATCH_SUBS subjects: the subject of a row from the
+    // subjects' first rows (wave-uniform loads), no extra payload word
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      int32_t sb = 0;
+      int64_t r0 = 0;
+#pragma unroll
+      for (int k = 1; k < BATCH_SUBS; ++k) {
+        if (k < job.nsub) {
+          const int64_t rk = job.subs[k].row0;
+          if (prow[g] >= rk) {
+            sb = k;
+            r0 = rk;
+          }
+        }
+      }
+      ext[g].y = __int_as_float(sb);
+      ext[g].z = __int_as_float((int32_t)(prow[g] - r0));
+    }
   }
   const Frame fr = frame(job.prm, Q);
   const float isf = (float)fr.is;  // a power of two
@@ -1067,6 +1095,7 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   float ulo[BOXD], uhi[BOXD];
   union_box<Q>(omin, omax, emax, isf, s_box[wave], ulo, uhi);
   s_best[wave][lane] = NO_KEY;
+  if (STATS) s_hit[wave][lane] = 0u;
   wave_lds_sync();
 
   auto negh = [&](int g) {
@@ -1110,6 +1139,7 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
         const uint32_t c = (uint32_t)job.ccent[col];
         const int32_t f = s_idx[wave][slot];
         const float* ar = frec(slot, f);
+        if (act) s_hit[wave][slot] = 1u;
         float D, v;
         const bool ok = exact_pair<true>(ar, job.csort + (size_t)col * CREC, act, D, sc, mt.flags);
         if (ok && variant_value(D, c, s_len[wave][slot], mt, v)) fold(slot, f, c, v);
@@ -1253,6 +1283,11 @@ __global__ __launch_bounds__(64 * CW) __attribute__((amdgpu_waves_per_eu(STATS |
   }
   if (nc) products(nc);
   if (qn) drain(qn);
+  if (STATS) {
+    wave_lds_sync();
+    const uint64_t hit = __ballot(s_hit[wave][lane] != 0u);
+    if (lane == 0 && hit) atomicAdd(counters + 6, (unsigned long long)__popcll(hit));
+  }
   // D: results of the rows with an accepted centroid
   if (!MULTI) {
     const unsigned long long best = s_best[wave][lane];
@@ -1539,7 +1574,8 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
     bb.citems_tab = bb.citems;
   }
   PfParams* prm = (PfParams*)pb.emax;
-  const Payload pay = payload_of(pb.fib_feat, rows, true);
+  const Payload pay_ext = payload_of(pb.fib_feat, rows, true);
+  const Payload pay_noext = payload_of(pb.fib_feat, rows, false);
   float* const csort = (float*)pb.cen_feat;
   uint32_t* keys_a = (uint32_t*)pb.keys;
   int32_t* vals_a = (int32_t*)pb.vals;
@@ -1554,6 +1590,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
       SubDev* csubs = dsubs + ch.sub0;
       int32_t* const* clab = dlab + (size_t)ch.sub0 * na;
       float* const* cdst = ddst + (size_t)ch.sub0 * na;
+      const Payload pay = tn || ch.nsub > BATCH_SUBS ? pay_ext : pay_noext;
       const FiberOut fo{pay, keys_a, nullptr, nullptr, csubs, ch.nsub, ch.blk, clab, cdst, na};
       const unsigned grid = (unsigned)(ch.blk < g ? ch.blk : g);
       if (tn)
@@ -1576,7 +1613,7 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
             at[a].cprep, m, ncols_pad, cperms[a], prm, cfeat, cbias, ccent, csort, tbox, sbox);
         const CullJob job{pay,    perm,    prm,      cfeat,      cbias, ccent,  tbox,
                           sbox,   ntiles,  nsuper,   nullptr,    ch.rows, csort,
-                          at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a};
+                          at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a, ch.nsub};
         const MultiOut mout{nullptr, 0, nullptr, nullptr};
         cull_kernel<Q, false, false, true>
             <<<(unsigned)((ch.rows + 64 * CW - 1) / (64 * CW)), 64 * CW, 0, cs>>>(

@@ -167,7 +167,8 @@ __device__ __forceinline__ float d2(const Point& a, const Point& b) {
 
 // Survivor counters (filled only when statistics are requested).
 struct StageCounts {
-  unsigned long long* p;  // [0] filter pass, [1] test2, [2] test3, [3] accepted, [4] drains
+  unsigned long long* p;  // [0] filter pass, [1] test2, [2] test3, [3] accepted, [4] drains,
+                          // [5] bound tiles, [6] survivor rows (tile-culled form)
 };
 
 // Exact stage for one (fiber, centroid) pair per lane: the paper's tests 2-4

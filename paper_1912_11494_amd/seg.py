@@ -65,7 +65,7 @@ METRICS = {"": 0, "tn": METRIC_LENGTH_NORM, "dir": METRIC_DIRECTION,
 class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("pairs", "filter_pass", "test2_pass", "test3_pass", "accepted", "labelled",
-                 "drains", "bound_pairs")]
+                 "drains", "bound_pairs", "survivor_rows")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -291,3 +291,32 @@ def test_batch_culled_chunks_match_single_calls(seg):
                 assert torch.equal(outs[i][a][0], lab), (mode, i, a)
                 assert torch.equal(outs[i][a][1], dist), (mode, i, a)
         del outs
+
+
+@pytest.mark.parametrize("mode", ["fp16", "bf16"])
+def test_batch_culled_many_subjects(seg, mode):
+    """A tile-culled chunk of more than 16 subjects carries each row's subject
+    and index in an extra payload word (a smaller chunk derives them from the
+    subjects' first rows): 21 subjects, some empty or tiny, against the
+    oracle."""
+    import torch
+
+    atl = _atlases()
+    sizes = [0 if i % 7 == 3 else 37 * (i % 5) + 1 + 50 * (i % 3) for i in range(21)]
+    subs = _subjects(atl, sizes, seed=91)
+    d = torch.device("cuda:0")
+    ga = [_gpu_atlas(seg, a) for a in atl]
+    gf = [torch.from_numpy(f).to(d) for f in subs]
+    log(f"batch of {len(subs)} subjects mode={mode}")
+    outs = seg.segment_batch(ga, gf, mode=mode, tile=0)
+    torch.cuda.synchronize()
+    for i, f in enumerate(subs):
+        for a, at in enumerate(atl):
+            lab = outs[i][a][0].cpu().numpy()
+            dist = outs[i][a][1].cpu().numpy()
+            if len(f) == 0:
+                assert lab.size == 0
+                continue
+            l32, d32, _ = oracle.segment_f32(f, at.centroids, at.bundle_id, at.thresholds)
+            assert np.array_equal(lab, l32), (mode, i, a)
+            assert np.array_equal(dist, d32), (mode, i, a)

@@ -48,6 +48,8 @@ def _check(seg, fib, cen, bid, thr, mode, ctx, check_f64=True):
     acc = oracle.accepted_pairs_f32(fib, cen, bid, thr)
     assert st["accepted"] == len(acc), f"{ctx}: accepted {st['accepted']} vs oracle {len(acc)}"
     assert st["filter_pass"] >= st["accepted"]
+    # fibers with a survivor: every labelled fiber, at most one per survivor
+    assert int((lab >= 0).sum()) <= st["survivor_rows"] <= min(st["filter_pass"], len(fib))
     # whole tiles of 32 (padded) fibers x 32 (padded) columns are evaluated
     pad = lambda k: (k + 31) // 32 * 32
     assert st["bound_pairs"] <= pad(len(fib)) * pad(len(cen))
