@@ -1351,11 +1351,11 @@ int grow_sort(PrefilterBuf& pb, int64_t nk) {
 // unique composite keys c = cell << 15 | index (their order is the stable
 // order by cell), the sorted position of centroid i is the number of c below
 // its own.  rank_count_kernel: block (x, y) counts, for its 256 centroids i,
-// the c of centroid tile y (1024 of them, staged in LDS) below c_i, into
+// the c of centroid tile y (RANK_TILE of them, staged in LDS) below c_i, into
 // part[y][i]; rank_place_kernel adds the parts and writes cperm[pos] = i.
 // Plain integer sums, so the order is deterministic.
 constexpr int RANK_MAX = 16384;
-constexpr int RANK_TILE = 1024;
+constexpr int RANK_TILE = 256;
 __device__ __forceinline__ uint32_t comp_key(const float* __restrict__ cprep, int32_t i,
                                              const PfParams* __restrict__ prm) {
   return (center_cell(cprep + (int64_t)i * CREC, prm) << 15) | (uint32_t)i;

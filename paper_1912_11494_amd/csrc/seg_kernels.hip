@@ -24,7 +24,8 @@ namespace seg {
 // ---------------------------------------------------------------- preparation
 
 // One thread per centroid: copy the record, attach T2 of its bundle.  A bundle
-// id outside [0, B) gets T2 = -1 (never matches) and raises a flag.
+// id outside [0, B) gets T2 = -1 (never matches) and raises a flag.  The
+// threads also check the B thresholds for NaN (grid-stride over bundles).
 __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict__ cen, int64_t m,
                                                          const int32_t* __restrict__ bid,
                                                          const float* __restrict__ thr, int32_t nb,
@@ -34,6 +35,8 @@ __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict
                                                          float* __restrict__ cext,
                                                          unsigned int* __restrict__ flags) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t b = c; b < nb; b += (int64_t)gridDim.x * blockDim.x)
+    if (__builtin_isnan(thr[b])) atomicOr(flags, FLAG_NONFINITE);
   if (c >= m) {
     // padding up to a multiple of 8: a center test that never passes
     if (c < ((m + 7) & ~(int64_t)7)) {
@@ -344,7 +347,8 @@ int launch_prep_atlas(const float* cen, int64_t m, const int32_t* bid, const flo
     prep_atlas_kernel<<<(unsigned)((mp + 63) / 64), 64, 0, s>>>(cen, m, bid, thr, nb, cprep, ccen,
                                                                 bid_out, cext, flags);
   }
-  if (nb > 0) check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
+  else if (nb > 0)  // (prep_atlas_kernel checks the thresholds when it runs)
+    check_thresholds_kernel<<<(nb + 255) / 256, 256, 0, s>>>(thr, nb, flags);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
