@@ -103,15 +103,15 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift) {
 }
 
 // Digit counts of each block: hist[digit][block].
-__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __restrict__ keys,
-                                                             int64_t n, int shift,
-                                                             uint32_t* __restrict__ hist,
-                                                             int32_t nblocks) {
+// (block bx of the count; also run by blocks of the fused kernel below)
+__device__ __forceinline__ void rs_hist_block(int32_t bx, const uint32_t* __restrict__ keys,
+                                              int64_t n, int shift, uint32_t* __restrict__ hist,
+                                              int32_t nblocks) {
   __shared__ uint32_t s_cnt[RS_BINS];
   const int tid = (int)threadIdx.x;
   s_cnt[tid] = 0u;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * RS_IPB;
+  const int64_t base = (int64_t)bx * RS_IPB;
   uint32_t kr[RS_IPB / RS_THREADS];
 #pragma unroll
   for (int j = 0; j < RS_IPB / RS_THREADS; ++j) {
@@ -122,7 +122,13 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __r
   for (int j = 0; j < RS_IPB / RS_THREADS; ++j)
     if (base + (int64_t)j * RS_THREADS + tid < n) atomicAdd(&s_cnt[digit_of(kr[j], shift)], 1u);
   __syncthreads();
-  hist[(int64_t)tid * nblocks + blockIdx.x] = s_cnt[tid];
+  hist[(int64_t)tid * nblocks + bx] = s_cnt[tid];
+}
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             int32_t nblocks) {
+  rs_hist_block((int32_t)blockIdx.x, keys, n, shift, hist, nblocks);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns
@@ -774,7 +780,7 @@ __device__ __forceinline__ void half_wave_box(float* lo, float* hi, int nd) {
 // [TROWS][ntiles] and [TROWS][nsuper]).
 constexpr int SUPER = 8;  // tiles per super-tile (one column block)
 template <int Q>
-__global__ __launch_bounds__(256) void cull_column_kernel(const float* __restrict__ cprep,
+__device__ __forceinline__ void column_block(int32_t bx, int32_t nsuper, const float* __restrict__ cprep,
                                                           int32_t m, int32_t ncols_pad,
                                                           const int32_t* __restrict__ cperm,
                                                           const PfParams* __restrict__ prm,
@@ -786,7 +792,7 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
                                                           float* __restrict__ sbox) {
   using T = QTraits<Q>;
   __shared__ float s_t[SUPER][TROWS];
-  const int32_t col = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int32_t col = bx * 256 + (int32_t)threadIdx.x;
   float lo[BOXD], hi[BOXD];
   float r2 = -__builtin_inff();
 #pragma unroll
@@ -835,14 +841,49 @@ __global__ __launch_bounds__(256) void cull_column_kernel(const float* __restric
     }
   }
   __syncthreads();
-  const int32_t nsuper = (int32_t)gridDim.x;
   if (threadIdx.x < TROWS) {
     const int k = (int)threadIdx.x;
     float v = s_t[0][k];
     for (int j = 1; j < SUPER; ++j)
       v = k < BOXD ? fminf(v, s_t[j][k]) : fmaxf(v, s_t[j][k]);
-    sbox[(int64_t)k * nsuper + blockIdx.x] = v;
+    sbox[(int64_t)k * nsuper + bx] = v;
   }
+}
+
+// Arguments of the column blocks.
+struct ColArgs {
+  const float* cprep;
+  int32_t m, ncols_pad, nsuper;
+  const int32_t* cperm;
+  const PfParams* prm;
+  uint8_t* feat;
+  float* cb;
+  int32_t* ccent;
+  float* csort;
+  float* tbox;
+  float* sbox;
+};
+
+template <int Q>
+__global__ __launch_bounds__(256) void cull_column_kernel(ColArgs ca) {
+  column_block<Q>((int32_t)blockIdx.x, ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm,
+                  ca.feat, ca.cb, ca.ccent, ca.csort, ca.tbox, ca.sbox);
+}
+
+// The columns (blocks [0, nsuper), the longer work, dispatched first) and the
+// first radix count of the fibers (the next nb_hist blocks) in one launch:
+// they depend on nothing of each other, so the small column grid runs beside
+// the count.
+template <int Q>
+__global__ __launch_bounds__(256) void hist_column_kernel(const uint32_t* __restrict__ keys,
+                                                          int64_t n, uint32_t* __restrict__ hist,
+                                                          int32_t nb_hist, ColArgs ca) {
+  const int32_t bx = (int32_t)blockIdx.x;
+  if (bx < ca.nsuper)
+    column_block<Q>(bx, ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm, ca.feat, ca.cb,
+                    ca.ccent, ca.csort, ca.tbox, ca.sbox);
+  else
+    rs_hist_block(bx - ca.nsuper, keys, n, 0, hist, nb_hist);
 }
 
 // A chunk of at most this many subjects finds a row's subject from the
@@ -1315,9 +1356,10 @@ int grow(void** p, size_t* have, size_t want) {
 
 // Stable sort of n keys (15 bits) into a permutation: vals_b[k] = index of
 // the k-th smallest key.  keys_a holds the keys on entry; keys_b, vals_a,
-// vals_b and hist (RS_BINS * nblocks + RS_BINS) are scratch.
+// vals_b and hist (RS_BINS * nblocks + RS_BINS) are scratch.  `counted`: the
+// caller has already launched the first pass's digit count.
 int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, int32_t* vals_b,
-               uint32_t* hist, hipStream_t s) {
+               uint32_t* hist, hipStream_t s, bool counted = false) {
   if (n <= 0) return 0;
   const int32_t nblocks = (int32_t)((n + RS_IPB - 1) / RS_IPB);
   uint32_t* tot = hist + (size_t)RS_BINS * nblocks;
@@ -1325,7 +1367,8 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
   for (int pass = 0; pass < 2; ++pass) {
     const int shift = 8 * pass;
     const uint32_t* kin = pass == 0 ? keys_a : keys_b;
-    rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, shift, hist, nblocks);
+    if (pass > 0 || !counted)
+      rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, shift, hist, nblocks);
     rs_scan_rows_kernel<<<RS_BINS, RS_THREADS, 0, s>>>(hist, nblocks, tot);
     if (pass == 0)
       rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_a, nullptr, n, shift, hist, tot,
@@ -1387,6 +1430,7 @@ __global__ __launch_bounds__(256) void rank_place_kernel(const uint32_t* __restr
   const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
   if (i >= m) return;
   uint32_t pos = 0;
+#pragma unroll 8
   for (int32_t y = 0; y < tiles; ++y) pos += part[(int64_t)y * m + i];
   cperm[pos] = i;  // pos < m: the c are distinct
 }
@@ -1463,13 +1507,17 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
           fibers, n, prm, fo);
     }
   }
-  if (radix_sort(n, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, s)) return -1;
-  // sorted columns with tile boxes
+  // sorted columns with tile boxes, launched with the sort's first count
   float* tbox = (float*)pb.tbox;
   float* sbox = tbox + (size_t)TROWS * ntiles;
-  cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, s>>>(
-      cprep, m, ncols_pad, cperm_cached ? cperm_cached : cperm, prm, cfeat, cbias, ccent, csort,
-      tbox, sbox);
+  {
+    const ColArgs ca{cprep, m,     ncols_pad, nsuper, cperm_cached ? cperm_cached : cperm,
+                     prm,   cfeat, cbias,     ccent,  csort, tbox, sbox};
+    const int32_t nbh = (int32_t)((n + RS_IPB - 1) / RS_IPB);
+    hist_column_kernel<Q><<<(unsigned)(nbh + nsuper), 256, 0, s>>>(keys_a, n, (uint32_t*)pb.hist,
+                                                                   nbh, ca);
+  }
+  if (radix_sort(n, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, s, true)) return -1;
   const CullJob job{pay,    perm,  prm,     cfeat,   cbias,   ccent, tbox, sbox, ntiles,
                     nsuper, fibers, n,      csort,   bid,     labels,  dists, nullptr, nullptr,
                     nullptr, 0, 0};
@@ -1609,8 +1657,9 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
         float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
         int32_t* ccent = (int32_t*)(cbias + ncols_pad);
         float* sbox = tbox + (size_t)TROWS * ntiles;
-        cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(
-            at[a].cprep, m, ncols_pad, cperms[a], prm, cfeat, cbias, ccent, csort, tbox, sbox);
+        cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(ColArgs{
+            at[a].cprep, m, ncols_pad, nsuper, cperms[a], prm, cfeat, cbias, ccent, csort, tbox,
+            sbox});
         const CullJob job{pay,    perm,    prm,      cfeat,      cbias, ccent,  tbox,
                           sbox,   ntiles,  nsuper,   nullptr,    ch.rows, csort,
                           at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a, ch.nsub};

@@ -185,3 +185,31 @@ def test_culled_prepared_atlas_order(seg, mode):
         assert (s1["pairs"], s1["accepted"]) == (s2["pairs"], s2["accepted"])
     assert_parity(l2.cpu().numpy(), d2.cpu().numpy(), fib, at.centroids, at.bundle_id,
                   at.thresholds, ctx=f"prepared {mode}", check_f64=False)
+
+
+def test_culled_scratch_is_linear(seg):
+    """The library's scratch after tile-culled calls stays O(N + M): a new
+    stream's scratch (payload rows, sort state, columns and boxes) is at most
+    200 bytes per fiber plus 2 KB per centroid plus a fixed megabyte, and the
+    statistics count the fibers with a survivor for the culled form only."""
+    import torch
+
+    fib, at = synth.small_case(30000, 40, 25, seed=17)
+    f, c, b, t = to_gpu(fib, at.centroids, at.bundle_id, at.thresholds)
+    m = at.n_centroids
+    s = torch.cuda.Stream()
+    assert seg.scratch_bytes(s) == 0
+    with torch.cuda.stream(s):
+        for mode in MODES:
+            seg.segment(f, c, b, t, mode=mode, tile=CULL, stream=s)
+    s.synchronize()
+    used = seg.scratch_bytes(s)
+    log(f"  scratch {used} bytes for {len(fib)} fibers x {m} centroids")
+    assert 0 < used <= 200 * len(fib) + 2048 * m + (1 << 20)
+    seg.segment(f, c, b, t, mode="plain", stats=True)
+    torch.cuda.synchronize()
+    assert seg.query_stats()["survivor_rows"] == -1
+    seg.segment(f, c, b, t, mode="fp16", tile=CULL, stats=True)
+    torch.cuda.synchronize()
+    st = seg.query_stats()
+    assert 0 < st["survivor_rows"] <= len(fib)
