@@ -117,10 +117,17 @@ def traffic_for(kernel: str):
     return e.get("bytes_per_launch")
 
 
-def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
+SIZE_COUNTERS = ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+                 "TCC_EA0_RDREQ_DRAM_32B_sum"]
+
+
+def write_traffic(fetch_csv: str, write_csv: str, out_path: str, sizes_csv: str = None) -> None:
     """Summarise two rocprofv3 --pmc runs of this script with --copy-probe
     (FETCH_SIZE, then WRITE_SIZE) into HBM bytes per launch.  The 1 GiB device
-    copy in the same runs fixes the byte value of one counted KiB."""
+    copy in the same runs fixes the byte value of one counted KiB.  A third,
+    optional run counts the L2's read requests to memory by size (32, 64 and
+    128 bytes) and the DRAM reads in 32-byte units: the read bytes they add
+    up to are recorded beside the calibrated figure as a cross-check."""
     import collections
     import csv
 
@@ -170,6 +177,32 @@ def write_traffic(fetch_csv: str, write_csv: str, out_path: str) -> None:
         out[key] = {"kernel": k, "fetch_kib": f, "write_kib": w,
                     "bytes_per_launch": f * 1024.0 * cf + w * 1024.0 * cw,
                     "source_hash": source_hash()}
+    if sizes_csv:
+        sz = {c: per_kernel(sizes_csv, c) for c in SIZE_COUNTERS}
+
+        def sizes_of(vals):
+            n32, n64, n128, d32 = (sum(v) / len(v) for v in vals)
+            return {"rdreq_32b": n32, "rdreq_64b": n64, "rdreq_128b": n128, "dram_32b": d32,
+                    "read_bytes_by_size": 32.0 * n32 + 64.0 * n64 + 128.0 * n128,
+                    "dram_read_bytes": 32.0 * d32}
+
+        # the copy: dispatches of the copy kernel whose requests add up to
+        # about 1 GiB (the probe's, not torch's small copies)
+        cops = [k for k in sz[SIZE_COUNTERS[0]] if "copy" in k.lower()]
+        for k in cops:
+            per = [32.0 * a + 64.0 * b + 128.0 * c for a, b, c in
+                   zip(sz[SIZE_COUNTERS[0]][k], sz[SIZE_COUNTERS[1]][k], sz[SIZE_COUNTERS[2]][k])]
+            big = [i for i, v in enumerate(per) if abs(v - gib) < 0.05 * gib]
+            if big:
+                rs = sizes_of([[sz[c][k][i] for i in big] for c in SIZE_COUNTERS])
+                out["calibration"]["request_sizes"] = dict(rs, dispatches=len(big))
+                break
+        for prefix, key in TRAFFIC_KERNELS:
+            if key not in out:
+                continue
+            k = out[key]["kernel"]
+            if all(k in sz[c] for c in SIZE_COUNTERS):
+                out[key]["request_sizes"] = sizes_of([sz[c][k] for c in SIZE_COUNTERS])
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
@@ -664,14 +697,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="only summarise two rocprofv3 counter files into profiles/traffic.json")
+    ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
+                    help="only summarise rocprofv3 counter files (FETCH_SIZE, WRITE_SIZE and, "
+                         "optionally, read requests by size) into profiles/traffic.json")
     ap.add_argument("--counters-from", nargs="+", metavar="CSV",
                     help="only summarise rocprofv3 --pmc counter files (one per pass) into "
                          "profiles/counters.json")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"))
+        if len(args.traffic_from) not in (2, 3):
+            raise SystemExit("--traffic-from FETCH_CSV WRITE_CSV [SIZES_CSV]")
+        fcsv, wcsv = args.traffic_from[:2]
+        write_traffic(fcsv, wcsv, os.path.join(ROOT, "profiles", "traffic.json"),
+                      args.traffic_from[2] if len(args.traffic_from) == 3 else None)
         return
     if args.counters_from:
         write_counters(args.counters_from, os.path.join(ROOT, "profiles", "counters.json"))

@@ -57,6 +57,37 @@ def test_traffic_table(tmp_path):
     assert "cull_kernel:bf16" not in d
 
 
+def test_traffic_request_sizes(tmp_path):
+    """The optional third pass: read requests by size add up to read bytes per
+    launch, the probe copy's found among the copies by its 1 GiB."""
+    gib = float(1 << 30)
+    fetch = [(1, COPY, gib / 2048), (2, CULL, 1000.0)]
+    write = [(1, COPY, gib / 1024), (2, CULL, 40.0)]
+    # (32 B, 64 B, 128 B requests, DRAM 32-byte units) per dispatch
+    sizes = {1: (COPY, (0.0, 0.0, gib / 128, gib / 32)), 2: (CULL, (100.0, 50.0, 10.0, 300.0)),
+             3: (CULL, (300.0, 150.0, 30.0, 500.0)), 4: (COPY, (4.0, 0.0, 0.0, 4.0))}
+    fp, wp, sp, out = (tmp_path / n for n in ("f.csv", "w.csv", "s.csv", "t.json"))
+    _write(fp, "FETCH_SIZE", fetch)
+    _write(wp, "WRITE_SIZE", write)
+    with open(sp, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for d, (k, vals) in sizes.items():
+            for c, v in zip(bench.SIZE_COUNTERS, vals):
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c,
+                            "Counter_Value": v})
+    bench.write_traffic(str(fp), str(wp), str(out), str(sp))
+    d = json.loads(out.read_text())
+    rc = d["calibration"]["request_sizes"]
+    assert rc["dispatches"] == 1
+    assert rc["read_bytes_by_size"] == gib and rc["dram_read_bytes"] == gib
+    r = d["cull_kernel:fp16"]["request_sizes"]
+    assert r["rdreq_32b"] == 200.0 and r["rdreq_64b"] == 100.0 and r["rdreq_128b"] == 20.0
+    assert r["read_bytes_by_size"] == 32.0 * 200 + 64.0 * 100 + 128.0 * 20
+    assert r["dram_read_bytes"] == 32.0 * 400
+
+
 def test_counter_table(tmp_path):
     """Counter passes summarised per kernel: each counter averaged over the
     kernel's dispatches, ratios derived from them, other kernels left out."""
