@@ -103,12 +103,13 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift) {
 }
 
 // Digit counts of each block: hist[digit][block].
-// (block bx of the count; also run by blocks of the fused kernel below)
-__device__ __forceinline__ void rs_hist_block(int32_t bx, const uint32_t* __restrict__ keys,
-                                              int64_t n, int shift, uint32_t* __restrict__ hist,
-                                              int32_t nblocks) {
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             int32_t nblocks) {
   __shared__ uint32_t s_cnt[RS_BINS];
   const int tid = (int)threadIdx.x;
+  const int32_t bx = (int32_t)blockIdx.x;
   s_cnt[tid] = 0u;
   __syncthreads();
   const int64_t base = (int64_t)bx * RS_IPB;
@@ -123,12 +124,6 @@ __device__ __forceinline__ void rs_hist_block(int32_t bx, const uint32_t* __rest
     if (base + (int64_t)j * RS_THREADS + tid < n) atomicAdd(&s_cnt[digit_of(kr[j], shift)], 1u);
   __syncthreads();
   hist[(int64_t)tid * nblocks + bx] = s_cnt[tid];
-}
-__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t* __restrict__ keys,
-                                                             int64_t n, int shift,
-                                                             uint32_t* __restrict__ hist,
-                                                             int32_t nblocks) {
-  rs_hist_block((int32_t)blockIdx.x, keys, n, shift, hist, nblocks);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns
@@ -200,22 +195,33 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scan_rows_kernel(uint32_t* __re
 // where start[d] (the exclusive scan of the digit totals) is computed by
 // every block from the totals, so each digit's run of the block is written
 // contiguously.
-__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n,
-    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
-    int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
+// (block bx of the scatter, with its LDS in `L`; also run by blocks of a
+// launch that carries other work beside it)
+struct ScatterLds {
+  uint32_t cnt[RS_THREADS / 64][RS_BINS];
+  uint32_t lstart[RS_BINS];
+  uint32_t gstart[RS_BINS];
+  uint32_t tmp[RS_THREADS];
+  uint32_t key[RS_IPB];
+  int32_t val[RS_IPB];
+};
+__device__ __forceinline__ void rs_scatter_block(
+    int32_t bx, const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in,
+    int64_t n, int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
+    int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out,
+    ScatterLds& L) {
   constexpr int WAVES = RS_THREADS / 64;
-  __shared__ uint32_t s_cnt[WAVES][RS_BINS];
-  __shared__ uint32_t s_lstart[RS_BINS];
-  __shared__ uint32_t s_gstart[RS_BINS];
-  __shared__ uint32_t s_tmp[RS_THREADS];
-  __shared__ uint32_t s_key[RS_IPB];
-  __shared__ int32_t s_val[RS_IPB];
+  auto& s_cnt = L.cnt;
+  auto& s_lstart = L.lstart;
+  auto& s_gstart = L.gstart;
+  auto& s_tmp = L.tmp;
+  auto& s_key = L.key;
+  auto& s_val = L.val;
   const int tid = (int)threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   for (int w = 0; w < WAVES; ++w) s_cnt[w][tid] = 0u;
-  const int64_t bstart = (int64_t)blockIdx.x * RS_IPB;
+  const int64_t bstart = (int64_t)bx * RS_IPB;
   const int64_t wb = bstart + (int64_t)wave * RS_IPW;
   // the wave's keys and values, all loads in flight at once (the ranking
   // below depends on LDS state round by round, so loads issued there would
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     // start of digit d over all blocks: exclusive scan of the digit totals
     const uint32_t dstart = block_exclusive_scan(dtot[d], s_tmp, &all);
     s_lstart[d] = l;
-    s_gstart[d] = dstart + hist[(int64_t)d * nblocks + blockIdx.x];
+    s_gstart[d] = dstart + hist[(int64_t)d * nblocks + bx];
     for (int w = 0; w < WAVES; ++w) {
       s_cnt[w][d] = l;
       l += c[w];
@@ -288,6 +294,14 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
     if (keys_out) keys_out[g] = key;
     vals_out[g] = v;
   }
+}
+__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n,
+    int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
+    int32_t nblocks, uint32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
+  __shared__ ScatterLds L;
+  rs_scatter_block((int32_t)blockIdx.x, keys_in, vals_in, n, shift, hist, dtot, nblocks, keys_out,
+                   vals_out, L);
 }
 
 // Center-cell keys of fibers (stride NF) or prepared centroids (stride CREC).
@@ -789,9 +803,9 @@ __device__ __forceinline__ void column_block(int32_t bx, int32_t nsuper, const f
                                                           int32_t* __restrict__ ccent,
                                                           float* __restrict__ csort,
                                                           float* __restrict__ tbox,
-                                                          float* __restrict__ sbox) {
+                                                          float* __restrict__ sbox,
+                                                          float (*s_t)[TROWS]) {
   using T = QTraits<Q>;
-  __shared__ float s_t[SUPER][TROWS];
   const int32_t col = bx * 256 + (int32_t)threadIdx.x;
   float lo[BOXD], hi[BOXD];
   float r2 = -__builtin_inff();
@@ -866,24 +880,32 @@ struct ColArgs {
 
 template <int Q>
 __global__ __launch_bounds__(256) void cull_column_kernel(ColArgs ca) {
+  __shared__ float s_t[SUPER][TROWS];
   column_block<Q>((int32_t)blockIdx.x, ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm,
-                  ca.feat, ca.cb, ca.ccent, ca.csort, ca.tbox, ca.sbox);
+                  ca.feat, ca.cb, ca.ccent, ca.csort, ca.tbox, ca.sbox, s_t);
 }
 
 // The columns (blocks [0, nsuper), the longer work, dispatched first) and the
-// first radix count of the fibers (the next nb_hist blocks) in one launch:
-// they depend on nothing of each other, so the small column grid runs beside
-// the count.
+// first scatter of the fibers' sort (the next nb_sort blocks) in one launch:
+// they depend on nothing of each other, so the small column grid, a chain of
+// dependent loads and double arithmetic per column, runs beside the scatter.
 template <int Q>
-__global__ __launch_bounds__(256) void hist_column_kernel(const uint32_t* __restrict__ keys,
-                                                          int64_t n, uint32_t* __restrict__ hist,
-                                                          int32_t nb_hist, ColArgs ca) {
+__global__ __launch_bounds__(256) void scatter_column_kernel(
+    const uint32_t* __restrict__ keys_in, int64_t n, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ dtot, int32_t nb_sort, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out, ColArgs ca) {
+  static_assert(RS_THREADS == 256, "one block size for both kinds of block");
+  __shared__ union {
+    ScatterLds sc;
+    float t[SUPER][TROWS];
+  } lds;  // one kind of block each: the two share the block's LDS
   const int32_t bx = (int32_t)blockIdx.x;
   if (bx < ca.nsuper)
     column_block<Q>(bx, ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm, ca.feat, ca.cb,
-                    ca.ccent, ca.csort, ca.tbox, ca.sbox);
+                    ca.ccent, ca.csort, ca.tbox, ca.sbox, lds.t);
   else
-    rs_hist_block(bx - ca.nsuper, keys, n, 0, hist, nb_hist);
+    rs_scatter_block(bx - ca.nsuper, keys_in, nullptr, n, 0, hist, dtot, nb_sort, keys_out,
+                     vals_out, lds.sc);
 }
 
 // A chunk of at most this many subjects finds a row's subject from the
@@ -1354,29 +1376,29 @@ int grow(void** p, size_t* have, size_t want) {
   return 0;
 }
 
+// Digit counts of one pass and their scan; the digit totals follow the
+// per-block counts in `hist`.
+void radix_count(int pass, int64_t n, const uint32_t* kin, uint32_t* hist, hipStream_t s) {
+  const int32_t nblocks = (int32_t)((n + RS_IPB - 1) / RS_IPB);
+  rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, 8 * pass, hist, nblocks);
+  rs_scan_rows_kernel<<<RS_BINS, RS_THREADS, 0, s>>>(hist, nblocks,
+                                                     hist + (size_t)RS_BINS * nblocks);
+}
 // Stable sort of n keys (15 bits) into a permutation: vals_b[k] = index of
 // the k-th smallest key.  keys_a holds the keys on entry; keys_b, vals_a,
-// vals_b and hist (RS_BINS * nblocks + RS_BINS) are scratch.  `counted`: the
-// caller has already launched the first pass's digit count.
+// vals_b and hist (RS_BINS * nblocks + RS_BINS) are scratch.
 int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, int32_t* vals_b,
-               uint32_t* hist, hipStream_t s, bool counted = false) {
+               uint32_t* hist, hipStream_t s) {
   if (n <= 0) return 0;
   const int32_t nblocks = (int32_t)((n + RS_IPB - 1) / RS_IPB);
   uint32_t* tot = hist + (size_t)RS_BINS * nblocks;
   // pass 1: bits 0-7, input order as values; pass 2: bits 8-14
-  for (int pass = 0; pass < 2; ++pass) {
-    const int shift = 8 * pass;
-    const uint32_t* kin = pass == 0 ? keys_a : keys_b;
-    if (pass > 0 || !counted)
-      rs_hist_kernel<<<nblocks, RS_THREADS, 0, s>>>(kin, n, shift, hist, nblocks);
-    rs_scan_rows_kernel<<<RS_BINS, RS_THREADS, 0, s>>>(hist, nblocks, tot);
-    if (pass == 0)
-      rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_a, nullptr, n, shift, hist, tot,
-                                                       nblocks, keys_b, vals_a);
-    else
-      rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_b, vals_a, n, shift, hist, tot,
-                                                       nblocks, nullptr, vals_b);
-  }
+  radix_count(0, n, keys_a, hist, s);
+  rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_a, nullptr, n, 0, hist, tot, nblocks,
+                                                   keys_b, vals_a);
+  radix_count(1, n, keys_b, hist, s);
+  rs_scatter_kernel<<<nblocks, RS_THREADS, 0, s>>>(keys_b, vals_a, n, 8, hist, tot, nblocks,
+                                                   nullptr, vals_b);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1507,17 +1529,24 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
           fibers, n, prm, fo);
     }
   }
-  // sorted columns with tile boxes, launched with the sort's first count
+  // the fibers' sort (as radix_sort), with the sorted columns and their tile
+  // boxes launched beside its first scatter
   float* tbox = (float*)pb.tbox;
   float* sbox = tbox + (size_t)TROWS * ntiles;
   {
     const ColArgs ca{cprep, m,     ncols_pad, nsuper, cperm_cached ? cperm_cached : cperm,
                      prm,   cfeat, cbias,     ccent,  csort, tbox, sbox};
-    const int32_t nbh = (int32_t)((n + RS_IPB - 1) / RS_IPB);
-    hist_column_kernel<Q><<<(unsigned)(nbh + nsuper), 256, 0, s>>>(keys_a, n, (uint32_t*)pb.hist,
-                                                                   nbh, ca);
+    uint32_t* hist = (uint32_t*)pb.hist;
+    const int32_t nbs = (int32_t)((n + RS_IPB - 1) / RS_IPB);
+    uint32_t* tot = hist + (size_t)RS_BINS * nbs;
+    uint32_t* keys_b = keys_a + nk;
+    radix_count(0, n, keys_a, hist, s);
+    scatter_column_kernel<Q><<<(unsigned)(nsuper + nbs), 256, 0, s>>>(keys_a, n, hist, tot, nbs,
+                                                                      keys_b, vals_a, ca);
+    radix_count(1, n, keys_b, hist, s);
+    rs_scatter_kernel<<<nbs, RS_THREADS, 0, s>>>(keys_b, vals_a, n, 8, hist, tot, nbs, nullptr,
+                                                 perm);
   }
-  if (radix_sort(n, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, s, true)) return -1;
   const CullJob job{pay,    perm,  prm,     cfeat,   cbias,   ccent, tbox, sbox, ntiles,
                     nsuper, fibers, n,      csort,   bid,     labels,  dists, nullptr, nullptr,
                     nullptr, 0, 0};
