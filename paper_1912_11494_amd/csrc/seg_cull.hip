@@ -647,10 +647,13 @@ __global__ __launch_bounds__(CF_THREADS) void cull_fiber_kernel(const float* __r
               __float_as_uint(e32));
 }
 
-// Blocks of cull_fiber_kernel<Q, BATCH, TN> launched: half of what the
-// device holds at once (queried once per process and kernel); with every
-// slot filled the streams of reads and writes are spread over a wider
-// window of memory and the kernel ran about a tenth slower.
+// Blocks of cull_fiber_kernel<Q, BATCH, TN> launched: three per compute unit
+// (twelve waves), or fewer where fewer fit (queried once per process and
+// kernel).  The kernel streams its reads: with more blocks in flight the
+// reads and writes spread over a wider window of memory and it ran slower
+// (0.230 ms at three blocks per unit against 0.238-0.248 ms at two, two and
+// a half and four, with 2-byte codes at the paper's subject size).
+constexpr int CF_BLOCKS_PER_CU = 3;
 template <int Q, bool BATCH, bool TN>
 int64_t cf_grid() {
   static std::atomic<int64_t> g{0};
@@ -663,7 +666,7 @@ int64_t cf_grid() {
                                                      CF_THREADS, 0) != hipSuccess ||
         cus <= 0 || per <= 0)
       return 1024;
-    v = std::max<int64_t>((int64_t)cus * per / 2, cus);
+    v = (int64_t)cus * std::min(per, CF_BLOCKS_PER_CU);
     g.store(v, std::memory_order_relaxed);
   }
   return v;
