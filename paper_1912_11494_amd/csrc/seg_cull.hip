@@ -781,14 +781,34 @@ __device__ __forceinline__ void union_box(uint32_t* m, uint32_t* M, float emax, 
 }
 
 // Lowest / highest over the 32 lanes of each half wave.
-__device__ __forceinline__ void half_wave_box(float* lo, float* hi, int nd) {
-  for (int k = 0; k < nd; ++k) {
+// One DPP step of a minimum (MAX false) or maximum over lanes: each lane
+// whose row is in RMASK combines its value with the lane CTRL names.
+template <int CTRL, int RMASK, bool MAX>
+__device__ __forceinline__ float dpp_minmax(float v) {
+  const float o = __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, RMASK, 0xF, false));
+  return MAX ? fmaxf(v, o) : fminf(v, o);
+}
+// Minimum or maximum over each half wave (32 lanes), complete in lanes 31 and
+// 63: within quads, then rows of 16 (row rotations by 4 and 8), then row 0
+// (2) into row 1 (3) by row_bcast:15.  No LDS traffic, unlike shuffles.
+template <bool MAX>
+__device__ __forceinline__ float half_wave_minmax(float v) {
+  v = dpp_minmax<0xB1, 0xF, MAX>(v);   // quad_perm [1,0,3,2]
+  v = dpp_minmax<0x4E, 0xF, MAX>(v);   // quad_perm [2,3,0,1]
+  v = dpp_minmax<0x124, 0xF, MAX>(v);  // row_ror:4
+  v = dpp_minmax<0x128, 0xF, MAX>(v);  // row_ror:8
+  return dpp_minmax<0x142, 0xA, MAX>(v);  // row_bcast:15 into rows 1 and 3
+}
+// The box of each half wave's 32 columns (and its largest radius), complete
+// in the half's last lane.
+__device__ __forceinline__ void half_wave_box(float* lo, float* hi, float* r2) {
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {
-      lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
-      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
-    }
+  for (int k = 0; k < BOXD; ++k) {
+    lo[k] = half_wave_minmax<false>(lo[k]);
+    hi[k] = half_wave_minmax<true>(hi[k]);
   }
+  *r2 = half_wave_minmax<true>(*r2);
 }
 
 // Sorted columns: column j is centroid cperm[j]; each half wave writes the
@@ -828,20 +848,30 @@ __device__ __forceinline__ void column_block(int32_t bx, int32_t nsuper, const f
       const int32_t c = cperm[col];
       ccent[col] = c;
       const float* rec = cprep + (int64_t)c * CREC;
-      cb[col] = column_row<Q, MAP_SYM, KPC>(rec, false, prm, row, lo, hi, &r2);
-      // the record in column order, for the exact stage
+      cb[col] = column_row<Q, MAP_SYM, KPC, true>(rec, false, prm, row, lo, hi, &r2);
+      // the record in column order, for the exact stage, in two halves
+      // whose eight loads are all issued before their stores (left to
+      // itself the compiler pairs each load with its store and waits for
+      // every load in turn).  The empty asm (no instruction) takes the eight
+      // values, so the loads come before it and the stores after it.
+      const f4v* src = (const f4v*)rec;
+      f4v* dst = (f4v*)(csort + (int64_t)col * CREC);
+      f4v rv[16];
 #pragma unroll
-      for (int k = 0; k < CREC; k += 4)
-        *(float4*)(csort + (int64_t)col * CREC + k) = *(const float4*)(rec + k);
+      for (int k = 0; k < 16; ++k) rv[k] = src[k];
+      asm volatile("" ::"v"(rv[0]), "v"(rv[1]), "v"(rv[2]), "v"(rv[3]), "v"(rv[4]), "v"(rv[5]),
+                   "v"(rv[6]), "v"(rv[7]), "v"(rv[8]), "v"(rv[9]), "v"(rv[10]), "v"(rv[11]),
+                   "v"(rv[12]), "v"(rv[13]), "v"(rv[14]), "v"(rv[15])
+                   : "memory");
+#pragma unroll
+      for (int k = 0; k < 16; ++k) dst[k] = rv[k];
     }
   }
-  half_wave_box(lo, hi, BOXD);
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) r2 = fmaxf(r2, __shfl_xor(r2, off));
+  half_wave_box(lo, hi, &r2);
   const int32_t tile = col >> 5;
   const int32_t ntiles = ncols_pad >> 5;
   const int h = (int)(threadIdx.x >> 5);  // tile within the block
-  if ((threadIdx.x & 31) == 0) {
+  if ((threadIdx.x & 31) == 31) {  // the half's last lane holds its box
 #pragma unroll
     for (int k = 0; k < BOXD; ++k) {
       s_t[h][k] = lo[k];

@@ -201,9 +201,11 @@ __device__ __forceinline__ double gamma_acc(int kp) { return 4.0 * (kp + 2) * 0x
 
 // Quantise the features of one curve: packs the KP codes into `row` (16-byte
 // stores), returns |Xq|^2 in *nq and the error bound |Xq - X| in *e; both are
-// non-finite when a coordinate is.  With `xlo` / `xhi`, also returns float
-// bounds that contain each exact (unquantised) feature.
-template <int Q, int MAPK, int KP>
+// non-finite when a coordinate is.  With BOX, also returns in `xlo` / `xhi`
+// float bounds that contain each exact (unquantised) feature (a template flag
+// rather than a null test: comparing the address of a caller's local array
+// with null keeps that array in scratch memory).
+template <int Q, int MAPK, int KP, bool BOX = false>
 __device__ __forceinline__ void quantise_row(const float* __restrict__ p, bool rev,
                                              const PfParams* __restrict__ prm,
                                              uint8_t* __restrict__ row, double* nq_out,
@@ -228,7 +230,7 @@ __device__ __forceinline__ void quantise_row(const float* __restrict__ p, bool r
     nq += xq * xq;
     err += (xq - x[k]) * (xq - x[k]);
     nx += x[k] * x[k];
-    if (xlo) {
+    if (BOX) {
       // the double feature is within 2^-50 relative of the exact one
       const double sl = fabs(x[k]) * 0x1p-48;
       xlo[k] = __double2float_rd(x[k] - sl);
@@ -249,36 +251,24 @@ __device__ __forceinline__ void quantise_row(const float* __restrict__ p, bool r
 }
 
 // Features of fiber row f (quantised codes, the row constant -Ha and the
-// fiber's error bound); with `xlo` / `xhi` also bounds of its exact features,
-// which are the widest possible for a fiber that bypasses the cut.
+// fiber's error bound).
 template <int Q, int MAPK, int KP>
 __device__ __forceinline__ void fiber_feature_row(const float* __restrict__ p, int64_t f,
                                                   int64_t n, const PfParams* __restrict__ prm,
                                                   uint8_t* __restrict__ row,
-                                                  float* __restrict__ negh, float* e_out,
-                                                  float* xlo = nullptr, float* xhi = nullptr) {
+                                                  float* __restrict__ negh, float* e_out) {
   if (f >= n) {  // padding rows: zero features, never pass
 #pragma unroll
     for (int k = 0; k < KP * QTraits<Q>::bytes; k += 16) *(uint4*)(row + k) = make_uint4(0, 0, 0, 0);
     negh[f] = -__builtin_inff();
-    if (xlo)
-      for (int k = 0; k < KP; ++k) {
-        xlo[k] = __builtin_inff();
-        xhi[k] = -__builtin_inff();
-      }
     return;
   }
   double nq, e;
-  quantise_row<Q, MAPK, KP>(p, false, prm, row, &nq, &e, xlo, xhi);
+  quantise_row<Q, MAPK, KP>(p, false, prm, row, &nq, &e);
   if (!__builtin_isfinite(e)) {
     // a non-finite coordinate: bypass the cut (always survive) and leave the
     // error bound of the other fibers alone; the exact stage decides
     negh[f] = __builtin_inff();
-    if (xlo)
-      for (int k = 0; k < KP; ++k) {
-        xlo[k] = -__builtin_inff();
-        xhi[k] = __builtin_inff();
-      }
     return;
   }
   const double g = gamma_acc(KP);
@@ -289,11 +279,12 @@ __device__ __forceinline__ void fiber_feature_row(const float* __restrict__ p, i
 
 // Features and column constant cb of centroid record p (point order
 // reversed for `rev`).  cb = +inf: the column never passes (T < 0); -inf: it
-// always passes (T = +inf, or a non-finite coordinate).  With `xlo` / `xhi` /
-// `r2`, also bounds of the exact features (empty for a column that never
-// passes, unbounded for one that always does) and the squared radius
-// G * T2 / (1 - 8u) that contains |X(a) - X(b)|^2 of every accepted pair.
-template <int Q, int MAPK, int KP>
+// always passes (T = +inf, or a non-finite coordinate).  With BOX, also
+// bounds of the exact features in `xlo` / `xhi` (empty for a column that
+// never passes, unbounded for one that always does) and in `r2` the squared
+// radius G * T2 / (1 - 8u) that contains |X(a) - X(b)|^2 of every accepted
+// pair.
+template <int Q, int MAPK, int KP, bool BOX = false>
 __device__ __forceinline__ float column_row(const float* __restrict__ p, bool rev,
                                             const PfParams* __restrict__ prm,
                                             uint8_t* __restrict__ row, float* xlo = nullptr,
@@ -301,9 +292,10 @@ __device__ __forceinline__ float column_row(const float* __restrict__ p, bool re
   using MI = MapInfo<MAPK, KP>;
   const float t2 = p[NF];
   double nq, eb;
-  quantise_row<Q, MAPK, KP>(p, rev, prm, row, &nq, &eb, xlo, xhi);
+  quantise_row<Q, MAPK, KP, BOX>(p, rev, prm, row, &nq, &eb, xlo, xhi);
   if (!(t2 >= 0.0f)) {  // bundle never matches
-    if (xlo) {
+    if (BOX) {
+#pragma unroll
       for (int k = 0; k < KP; ++k) {
         xlo[k] = __builtin_inff();
         xhi[k] = -__builtin_inff();
@@ -314,8 +306,9 @@ __device__ __forceinline__ float column_row(const float* __restrict__ p, bool re
   }
   if (__builtin_isinf(t2) || !__builtin_isfinite(eb)) {
     // bundle always matches, or a non-finite coordinate: always survive
-    if (xlo) {
+    if (BOX) {
       if (!__builtin_isfinite(eb))
+#pragma unroll
         for (int k = 0; k < KP; ++k) {
           xlo[k] = -__builtin_inff();
           xhi[k] = __builtin_inff();
@@ -329,7 +322,7 @@ __device__ __forceinline__ float column_row(const float* __restrict__ p, bool re
   for (int i = 0; i < EMAX_SLOTS; ++i) eb_bits = max(eb_bits, prm->emax_bits[i]);
   const double E = (double)__uint_as_float(eb_bits);
   const double R2 = (double)MI::G * (double)t2 / (1.0 - 8.0 * 0x1p-24) * (1.0 + 0x1p-40);
-  if (r2) *r2 = __double2float_ru(R2);
+  if (BOX) *r2 = __double2float_ru(R2);
   const double R = sqrt(R2) * (1.0 + 0x1p-40);
   const double S = (R + E + eb) * (1.0 + 0x1p-40);
   const double g = gamma_acc(KP);
