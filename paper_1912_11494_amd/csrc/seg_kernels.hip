@@ -54,18 +54,23 @@ __global__ __launch_bounds__(256) void prep_atlas_kernel(const float* __restrict
   } else {
     atomicOr(flags, FLAG_BUNDLE);
   }
+  // the record in registers: every load issued before the first store, and
+  // the arc length taken from the registers, not re-read from the copy
+  float v[CREC];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) v[k] = src[k];
+  v[NF] = t2;
   bool finite = true;
-  for (int k = 0; k < NF; ++k) {
-    float v = src[k];
-    finite = finite && __builtin_isfinite(v);
-    dst[k] = v;
-  }
-  dst[NF] = t2;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) finite = finite && __builtin_isfinite(v[k]);
+#pragma unroll
+  for (int k = 0; k < CREC; k += 4)
+    *(float4*)(dst + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
   if (!finite) atomicOr(flags, FLAG_NONFINITE);
-  ccen[c] = make_float4(src[3 * CTR], src[3 * CTR + 1], src[3 * CTR + 2], t2);
+  ccen[c] = make_float4(v[3 * CTR], v[3 * CTR + 1], v[3 * CTR + 2], t2);
   bid_out[c] = b;
   // for the length-normalised metric: arc length and threshold T
-  cext[2 * c] = arc_length(dst);
+  cext[2 * c] = arc_length(v);
   cext[2 * c + 1] = (b >= 0 && b < nb) ? thr[b] : -1.0f;
 }
 
