@@ -58,10 +58,10 @@ __global__ void pf_init_kernel(PfParams* __restrict__ prm) {
 }
 
 // Bounding box of the centroid coordinates: the prepared records read as one
-// flat array of 16-byte words (coalesced, grid-stride), each float sorted to
-// its axis by its place in the 64-float record (the last float, T2, is not a
-// coordinate); reduced over the wave and the block, then one atomic per block
-// and axis.
+// flat array of 16-byte words (coalesced, grid-stride, four words per thread
+// in flight at once), each float sorted to its axis by its place in the
+// 64-float record (the last float, T2, is not a coordinate); reduced over the
+// wave and the block, then one atomic per block and axis.
 constexpr int BBOX_BLOCK = 256, BBOX_GRID = 64;
 __global__ __launch_bounds__(BBOX_BLOCK) void pf_bbox_kernel(const float* __restrict__ cprep,
                                                              int32_t m,
@@ -71,23 +71,34 @@ __global__ __launch_bounds__(BBOX_BLOCK) void pf_bbox_kernel(const float* __rest
   float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
   float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
   const int64_t nq = (int64_t)m * (CREC / 4);
-  for (int64_t q = (int64_t)blockIdx.x * BBOX_BLOCK + threadIdx.x; q < nq;
-       q += (int64_t)gridDim.x * BBOX_BLOCK) {
-    const float4 v4 = *(const float4*)(cprep + 4 * q);
-    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
-    const int pos0 = (int)((4 * q) & (CREC - 1));
+  const int64_t stride = (int64_t)gridDim.x * BBOX_BLOCK;
+  constexpr int U = 4;  // words per thread and round, all loads in flight together
+  for (int64_t q0 = (int64_t)blockIdx.x * BBOX_BLOCK + threadIdx.x; q0 < nq; q0 += U * stride) {
+    float4 w[U];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pos = pos0 + i;
-      if (pos < NF && __builtin_isfinite(v[i])) {
-        const int d = pos % 3;
-        // select by axis without a dynamically indexed register array
-        lo[0] = d == 0 ? fminf(lo[0], v[i]) : lo[0];
-        hi[0] = d == 0 ? fmaxf(hi[0], v[i]) : hi[0];
-        lo[1] = d == 1 ? fminf(lo[1], v[i]) : lo[1];
-        hi[1] = d == 1 ? fmaxf(hi[1], v[i]) : hi[1];
-        lo[2] = d == 2 ? fminf(lo[2], v[i]) : lo[2];
-        hi[2] = d == 2 ? fmaxf(hi[2], v[i]) : hi[2];
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = q0 + u * stride;
+      w[u] = q < nq ? *(const float4*)(cprep + 4 * q)
+                    : make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""),
+                                  __builtin_nanf(""));  // past the end: skipped below
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float v[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+      const int pos0 = (int)((4 * (q0 + u * stride)) & (CREC - 1));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pos = pos0 + i;
+        if (pos < NF && __builtin_isfinite(v[i])) {
+          const int d = pos % 3;
+          // select by axis without a dynamically indexed register array
+          lo[0] = d == 0 ? fminf(lo[0], v[i]) : lo[0];
+          hi[0] = d == 0 ? fmaxf(hi[0], v[i]) : hi[0];
+          lo[1] = d == 1 ? fminf(lo[1], v[i]) : lo[1];
+          hi[1] = d == 1 ? fmaxf(hi[1], v[i]) : hi[1];
+          lo[2] = d == 2 ? fminf(lo[2], v[i]) : lo[2];
+          hi[2] = d == 2 ? fmaxf(hi[2], v[i]) : hi[2];
+        }
       }
     }
   }
