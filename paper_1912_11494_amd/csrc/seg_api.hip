@@ -43,7 +43,8 @@ struct AtlasBuf {
   float4* ccen = nullptr;   // [m_pad]
   int32_t* bid = nullptr;   // [m_pad]
   float* cext = nullptr;    // [m_pad][2]: arc length, threshold T
-  int32_t* cperm = nullptr; // [m_pad]: tile-culled centroid order (a prepared atlas)
+  int32_t* cperm = nullptr; // [m_pad + 8]: tile-culled centroid order (a prepared atlas),
+                            // then its frame at [m, m + 6)
   bool cperm_ok = false;    // cperm holds this atlas's order
   int64_t cap = 0;          // capacity in centroids
   int64_t m = 0;
@@ -56,7 +57,7 @@ struct AtlasBuf {
     HIP_TRY(hipMalloc(&ccen, (size_t)mp * sizeof(float4)));
     HIP_TRY(hipMalloc(&bid, (size_t)mp * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&cext, (size_t)mp * 2 * sizeof(float)));
-    HIP_TRY(hipMalloc(&cperm, (size_t)mp * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&cperm, (size_t)(mp + 8) * sizeof(int32_t)));
     cap = mp;
     return 0;
   }

@@ -1509,6 +1509,26 @@ int sort_centroids(const float* cprep, int32_t m, const PfParams* prm, Prefilter
   return radix_sort(m, keys_a, keys_a + nk, vals_a, cperm, (uint32_t*)pb.hist, s);
 }
 
+// The frame of a prepared atlas (its box, as order-preserving integers) kept
+// after its centroid order: saved once, loaded by each call in place of the
+// box reduction, with the fiber error slots reset as a fresh frame has them.
+__global__ void frame_save_kernel(const PfParams* __restrict__ prm, int* __restrict__ out) {
+  const int t = (int)threadIdx.x;
+  if (t < 3) {
+    out[t] = prm->lo[t];
+    out[3 + t] = prm->hi[t];
+  }
+}
+__global__ void frame_load_kernel(PfParams* __restrict__ prm, const int* __restrict__ in) {
+  const int t = (int)threadIdx.x;
+  if (t < 3) {
+    prm->lo[t] = in[t];
+    prm->hi[t] = in[3 + t];
+  }
+  if (t < EMAX_SLOTS) prm->emax_bits[t] = 0u;
+}
+static_assert(EMAX_SLOTS <= 64, "one 64-thread block resets every slot");
+
 template <int Q>
 int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, const int32_t* bid,
                 int32_t* labels, float* dists, unsigned long long* counters, Metric mt,
@@ -1541,7 +1561,12 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   int32_t* vals_a = (int32_t*)pb.vals;
   int32_t* perm = vals_a + nk;
   int32_t* cperm = (int32_t*)pb.cperm;
-  if (launch_pf_setup(prm, cprep, m, s)) return -1;
+  // the frame: kept with a prepared atlas (after its centroid order), else
+  // the box of the atlas points
+  if (cperm_cached)
+    frame_load_kernel<<<1, 64, 0, s>>>(prm, (const int*)(cperm_cached + m));
+  else if (launch_pf_setup(prm, cprep, m, s))
+    return -1;
   // centroids: their order (unless the prepared atlas holds it)
   if (!cperm_cached) {
     rc = sort_centroids(cprep, m, prm, pb, nk, cperm, s);
@@ -1784,7 +1809,10 @@ int cull_sort_centroids(const float* cprep, int32_t m, int32_t* cperm_out, Prefi
   if (!pb.emax && hipMalloc((void**)&pb.emax, sizeof(PfParams)) != hipSuccess) return -3;
   PfParams* prm = (PfParams*)pb.emax;
   if (launch_pf_setup(prm, cprep, m, s)) return -1;
-  return sort_centroids(cprep, m, prm, pb, m, cperm_out, s);
+  rc = sort_centroids(cprep, m, prm, pb, m, cperm_out, s);
+  if (rc) return rc;
+  frame_save_kernel<<<1, 64, 0, s>>>(prm, (int*)(cperm_out + m));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace seg

@@ -104,7 +104,8 @@ int launch_plain_pairs(const float* fibers, int64_t n, const float4* ccen, int32
 // Prefilter modes (seg_prefilter.hip).  Return 0, -1 on a HIP error, -2 on an
 // unsupported mode or tile, -3 on a failed allocation.
 // `cperm`, when not null, is the atlas's sorted column order computed once by
-// cull_sort_centroids (the tile-culled form then skips that sort).
+// cull_sort_centroids, followed by its frame (the tile-culled form then skips
+// that sort and the box reduction).
 int run_prefilter(int mode, int cfg, const float* fibers, int64_t n, const float* cprep,
                   const float4* ccen, int32_t m, const int32_t* bid, int32_t* labels,
                   float* dists, unsigned long long* counters, Metric mt, PrefilterBuf& pb,
@@ -134,7 +135,9 @@ int run_cull_batch(int q, const BatchAtlas* atlases, int32_t n_atlases,
                    hipStream_t s);
 // The tile-culled form's centroid order for a prepared atlas: centroids
 // sorted by the cell of their center point in the atlas's frame (the same for
-// every subject and quantisation), written to cperm_out [m].
+// every subject and quantisation), written to cperm_out [m], and the frame
+// itself (six words) after it, at cperm_out [m, m + 6): cperm_out holds
+// m + 6 entries.  run_cull reads the frame there when given the order.
 int cull_sort_centroids(const float* cprep, int32_t m, int32_t* cperm_out, PrefilterBuf& pb,
                         hipStream_t s);
 
