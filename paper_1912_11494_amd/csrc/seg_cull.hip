@@ -918,27 +918,39 @@ __global__ __launch_bounds__(256) void cull_column_kernel(ColArgs ca) {
                   ca.feat, ca.cb, ca.ccent, ca.csort, ca.tbox, ca.sbox, s_t);
 }
 
-// The columns (blocks [0, nsuper), the longer work, dispatched first) and the
-// first scatter of the fibers' sort (the next nb_sort blocks) in one launch:
-// they depend on nothing of each other, so the small column grid, a chain of
-// dependent loads and double arithmetic per column, runs beside the scatter.
+// The columns of up to COL_MAX atlases (blocks [first[i], first[i + 1]) for
+// atlas i: the longer work, dispatched first) and the first scatter of the
+// fibers' sort (the remaining nb_sort blocks) in one launch: they depend on
+// nothing of each other, so the small column grids, a chain of dependent
+// loads and double arithmetic per column, run beside the scatter.
+constexpr int COL_MAX = 4;
+struct ColSet {
+  ColArgs c[COL_MAX];
+  int32_t first[COL_MAX + 1];
+  int32_t n;
+};
 template <int Q>
 __global__ __launch_bounds__(256) void scatter_column_kernel(
     const uint32_t* __restrict__ keys_in, int64_t n, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ dtot, int32_t nb_sort, uint32_t* __restrict__ keys_out,
-    int32_t* __restrict__ vals_out, ColArgs ca) {
+    int32_t* __restrict__ vals_out, ColSet cs) {
   static_assert(RS_THREADS == 256, "one block size for both kinds of block");
   __shared__ union {
     ScatterLds sc;
     float t[SUPER][TROWS];
   } lds;  // one kind of block each: the two share the block's LDS
   const int32_t bx = (int32_t)blockIdx.x;
-  if (bx < ca.nsuper)
-    column_block<Q>(bx, ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm, ca.feat, ca.cb,
-                    ca.ccent, ca.csort, ca.tbox, ca.sbox, lds.t);
-  else
-    rs_scatter_block(bx - ca.nsuper, keys_in, nullptr, n, 0, hist, dtot, nb_sort, keys_out,
+  if (bx < cs.first[cs.n]) {
+    int i = 0;
+#pragma unroll
+    for (int k = 1; k < COL_MAX; ++k) i += (k < cs.n && bx >= cs.first[k]) ? 1 : 0;
+    const ColArgs& ca = cs.c[i];
+    column_block<Q>(bx - cs.first[i], ca.nsuper, ca.cprep, ca.m, ca.ncols_pad, ca.cperm, ca.prm,
+                    ca.feat, ca.cb, ca.ccent, ca.csort, ca.tbox, ca.sbox, lds.t);
+  } else {
+    rs_scatter_block(bx - cs.first[cs.n], keys_in, nullptr, n, 0, hist, dtot, nb_sort, keys_out,
                      vals_out, lds.sc);
+  }
 }
 
 // A chunk of at most this many subjects finds a row's subject from the
@@ -1435,6 +1447,22 @@ int radix_sort(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a, i
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The fibers' sort (as radix_sort) with the column sets of `cs` computed
+// beside its first scatter.
+template <int Q>
+int sort_with_columns(int64_t n, uint32_t* keys_a, uint32_t* keys_b, int32_t* vals_a,
+                      int32_t* perm, uint32_t* hist, const ColSet& cs, hipStream_t s) {
+  const int32_t nbs = (int32_t)((n + RS_IPB - 1) / RS_IPB);
+  uint32_t* tot = hist + (size_t)RS_BINS * nbs;
+  radix_count(0, n, keys_a, hist, s);
+  scatter_column_kernel<Q><<<(unsigned)(cs.first[cs.n] + nbs), 256, 0, s>>>(
+      keys_a, n, hist, tot, nbs, keys_b, vals_a, cs);
+  radix_count(1, n, keys_b, hist, s);
+  rs_scatter_kernel<<<nbs, RS_THREADS, 0, s>>>(keys_b, vals_a, n, 8, hist, tot, nbs, nullptr,
+                                               perm);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // Sort scratch for up to nk keys: keys (two buffers), values (two buffers;
 // the second is the permutation) and the digit counts.
 int grow_sort(PrefilterBuf& pb, int64_t nk) {
@@ -1592,18 +1620,14 @@ int cull_launch(const float* fibers, int64_t n, const float* cprep, int32_t m, c
   float* tbox = (float*)pb.tbox;
   float* sbox = tbox + (size_t)TROWS * ntiles;
   {
-    const ColArgs ca{cprep, m,     ncols_pad, nsuper, cperm_cached ? cperm_cached : cperm,
-                     prm,   cfeat, cbias,     ccent,  csort, tbox, sbox};
-    uint32_t* hist = (uint32_t*)pb.hist;
-    const int32_t nbs = (int32_t)((n + RS_IPB - 1) / RS_IPB);
-    uint32_t* tot = hist + (size_t)RS_BINS * nbs;
-    uint32_t* keys_b = keys_a + nk;
-    radix_count(0, n, keys_a, hist, s);
-    scatter_column_kernel<Q><<<(unsigned)(nsuper + nbs), 256, 0, s>>>(keys_a, n, hist, tot, nbs,
-                                                                      keys_b, vals_a, ca);
-    radix_count(1, n, keys_b, hist, s);
-    rs_scatter_kernel<<<nbs, RS_THREADS, 0, s>>>(keys_b, vals_a, n, 8, hist, tot, nbs, nullptr,
-                                                 perm);
+    ColSet cs{};
+    cs.c[0] = ColArgs{cprep, m,     ncols_pad, nsuper, cperm_cached ? cperm_cached : cperm,
+                      prm,   cfeat, cbias,     ccent,  csort, tbox, sbox};
+    cs.first[0] = 0;
+    cs.first[1] = nsuper;
+    cs.n = 1;
+    if (sort_with_columns<Q>(n, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs, s))
+      return -1;
   }
   const CullJob job{pay,    perm,  prm,     cfeat,   cbias,   ccent, tbox, sbox, ntiles,
                     nsuper, fibers, n,      csort,   bid,     labels,  dists, nullptr, nullptr,
@@ -1668,17 +1692,23 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   const int32_t nsub = (int32_t)subs.size();
   int32_t mmax = 1;
   for (int32_t a = 0; a < na; ++a) mmax = std::max(mmax, at[a].m);
-  const int32_t cpad_max = (mmax + 31) / 32 * 32;
-  const int32_t tiles_max = cpad_max / 32;
-  const int32_t super_max = (cpad_max + 255) / 256;
   const int64_t nk = std::max<int64_t>(rows, mmax);
+  // each atlas its own columns (records, codes, constants, centroids) and
+  // tile boxes, so that the columns of several atlases are built together
+  std::vector<size_t> col_off(na), box_off(na);
+  size_t col_bytes = 0, box_floats = 0;
+  for (int32_t a = 0; a < na; ++a) {
+    const int64_t cpad = at[a].m > 0 ? ((int64_t)at[a].m + 31) / 32 * 32 : 0;
+    col_off[a] = col_bytes;
+    col_bytes += ((size_t)cpad * (CREC_BYTES + KPC * EB + 2 * sizeof(float)) + 255) / 256 * 256;
+    box_off[a] = box_floats;
+    box_floats += (size_t)TROWS * (cpad / 32 + (cpad + 255) / 256);
+  }
   // scratch (allocated before any capture)
   int rc = grow(&pb.fib_feat, &pb.fib_feat_bytes, (size_t)rows * PAY_BYTES);
   rc = rc ? rc : grow_sort(pb, nk);
-  rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes,
-                      (size_t)cpad_max * (CREC_BYTES + KPC * EB + 2 * sizeof(float)));
-  rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes,
-                      (size_t)TROWS * (tiles_max + super_max) * sizeof(float));
+  rc = rc ? rc : grow(&pb.cen_feat, &pb.cen_feat_bytes, std::max<size_t>(col_bytes, 256));
+  rc = rc ? rc : grow(&pb.tbox, &pb.tbox_bytes, std::max<size_t>(box_floats, 64) * sizeof(float));
   const size_t tab = (size_t)nsub * sizeof(SubDev) + olab.size() * 2 * sizeof(void*);
   rc = rc ? rc : grow(&bb.citems, &bb.citems_bytes, tab);
   if (rc) return rc;
@@ -1711,13 +1741,26 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
   PfParams* prm = (PfParams*)pb.emax;
   const Payload pay_ext = payload_of(pb.fib_feat, rows, true);
   const Payload pay_noext = payload_of(pb.fib_feat, rows, false);
-  float* const csort = (float*)pb.cen_feat;
   uint32_t* keys_a = (uint32_t*)pb.keys;
   int32_t* vals_a = (int32_t*)pb.vals;
   int32_t* perm = vals_a + nk;
   float* tbox = (float*)pb.tbox;
   const bool tn = (mflags & MF_TN) != 0;
   const int64_t g = tn ? cf_grid<Q, true, true>() : cf_grid<Q, true, false>();
+  // atlas a's columns and boxes in its own regions
+  auto col_args = [&](int32_t a) {
+    const int32_t m = at[a].m;
+    const int32_t ncols_pad = (m + 31) / 32 * 32;
+    const int32_t ntiles = ncols_pad / 32;
+    const int32_t nsuper = (ncols_pad + 255) / 256;
+    float* csort = (float*)((uint8_t*)pb.cen_feat + col_off[a]);
+    uint8_t* cfeat = (uint8_t*)(csort + (size_t)ncols_pad * CREC);
+    float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
+    int32_t* ccent = (int32_t*)(cbias + ncols_pad);
+    float* tb = tbox + box_off[a];
+    return ColArgs{at[a].cprep, m,     ncols_pad, nsuper, cperms[a], prm,
+                   cfeat,       cbias, ccent,     csort,  tb,        tb + (size_t)TROWS * ntiles};
+  };
   auto enqueue = [&](hipStream_t cs) -> int {
     launch_pf_init(prm, cs);
     for (int32_t a = 0; a < na; ++a) launch_pf_bbox_acc(prm, at[a].cprep, at[a].m, cs);
@@ -1732,23 +1775,28 @@ int cull_batch_launch(const BatchAtlas* at, int32_t na, const int32_t* const* cp
         cull_fiber_kernel<Q, true, true><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
       else
         cull_fiber_kernel<Q, true, false><<<grid, CF_THREADS, 0, cs>>>(nullptr, 0, prm, fo);
-      if (radix_sort(ch.rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist, cs))
+      // the sort, with the columns of the first COL_MAX atlases beside its
+      // first scatter (the columns depend on the chunk through the largest
+      // fiber error so far)
+      ColSet set{};
+      std::vector<bool> in_set(na, false);
+      for (int32_t a = 0; a < na && set.n < COL_MAX; ++a) {
+        if (at[a].m <= 0) continue;
+        set.c[set.n] = col_args(a);
+        set.first[set.n + 1] = set.first[set.n] + set.c[set.n].nsuper;
+        in_set[a] = true;
+        ++set.n;
+      }
+      if (sort_with_columns<Q>(ch.rows, keys_a, keys_a + nk, vals_a, perm, (uint32_t*)pb.hist,
+                               set, cs))
         return -1;
       for (int32_t a = 0; a < na; ++a) {
-        const int32_t m = at[a].m;
-        if (m <= 0) continue;  // every output already holds (-1, +inf)
-        const int32_t ncols_pad = (m + 31) / 32 * 32;
-        const int32_t ntiles = ncols_pad / 32;
-        const int32_t nsuper = (ncols_pad + 255) / 256;
-        uint8_t* cfeat = (uint8_t*)(csort + (size_t)ncols_pad * CREC);
-        float* cbias = (float*)(cfeat + (size_t)ncols_pad * KPC * EB);
-        int32_t* ccent = (int32_t*)(cbias + ncols_pad);
-        float* sbox = tbox + (size_t)TROWS * ntiles;
-        cull_column_kernel<Q><<<(unsigned)nsuper, 256, 0, cs>>>(ColArgs{
-            at[a].cprep, m, ncols_pad, nsuper, cperms[a], prm, cfeat, cbias, ccent, csort, tbox,
-            sbox});
-        const CullJob job{pay,    perm,    prm,      cfeat,      cbias, ccent,  tbox,
-                          sbox,   ntiles,  nsuper,   nullptr,    ch.rows, csort,
+        if (at[a].m <= 0) continue;  // every output already holds (-1, +inf)
+        const ColArgs ca = col_args(a);
+        if (!in_set[a]) cull_column_kernel<Q><<<(unsigned)ca.nsuper, 256, 0, cs>>>(ca);
+        const int32_t ntiles = ca.ncols_pad / 32;
+        const CullJob job{pay,    perm,    prm,      ca.feat,    ca.cb, ca.ccent, ca.tbox,
+                          ca.sbox, ntiles, ca.nsuper, nullptr,   ch.rows, ca.csort,
                           at[a].bid, nullptr, nullptr, csubs, clab,  cdst,   na, a, ch.nsub};
         const MultiOut mout{nullptr, 0, nullptr, nullptr};
         cull_kernel<Q, false, false, true>
