@@ -24,19 +24,21 @@
 // scatters with ranks from wave ballots, so equal keys keep their input
 // order and the permutation is deterministic.
 //
-// Fiber payloads (feature codes, row constant, error bound; arc length and
-// subject where needed) are computed in input order, four lanes per fiber,
-// and written as whole memory lines; the culled kernel gathers its rows
-// through the permutation.
+// Fiber payloads (feature codes and error bound, the row constant with
+// 1-byte codes; arc length and subject where needed) are computed in input
+// order, four lanes per fiber, and written as whole memory lines; the culled
+// kernel gathers its rows through the permutation.
 //
 // Work per wave (64 consecutive sorted rows = 2 groups of 32; the four
 // waves of a block run independently):
-//   A. each lane tests its centroid tiles against the union box of the
-//      wave's two groups, and a passing tile against each group; (tile,
-//      groups) candidates go to an LDS list, 256 tiles per round;
-//   B. for each candidate, the MFMA bound on the (tile, group) products, the
-//      next candidate's column fragment loading meanwhile; pairs at or above
-//      the column constant go to the wave's LDS survivor queue;
+//   A. the union box of the wave's rows (widened by their largest error
+//      bound) is tested against the boxes of the super-tiles (8 tiles of 32
+//      columns), then against the tiles of the passing super-tiles, one
+//      tile per lane; passing tiles go to an LDS list, 256 per round;
+//   B. for each listed tile, the MFMA bound on its products with each group
+//      (group 1 only when it holds a row), the columns of the next three
+//      tiles loading meanwhile; pairs at or above the column constant go to
+//      the wave's LDS survivor queue;
 //   C. the exact float32 stage on the queued pairs (when the queue fills and
 //      at the end), four lanes per pair, each lane taking the point pairs
 //      (i, 20 - i) of three values of i; accepted pairs fold into the
